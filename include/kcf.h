@@ -1,0 +1,172 @@
+/*
+ * kcf.h — C ABI of the MI355X (gfx950) library for explicit filtering, Favre filtering,
+ * subgrid-scale (SGS) tensors, closure expressions and a learned SGS closure on periodic
+ * 3-D grids.
+ *
+ * The quantities follow the definitions of the kinetic-closure paper (Marson & Malaspinas,
+ * "Kinetic closure of turbulence: collision-side modeling beyond the filtered Boltzmann
+ * equation"):
+ *   - homogeneous LES filter bar(.) of uniform width Delta (Sec. "Filtered nondimensional
+ *     recorrelated BGK-BE"; the kernel shape is not prescribed there, so the library offers
+ *     a trapezoidal box and a truncated Gaussian, see kcf_filter_taps);
+ *   - Favre velocity ut_i = bar(rho u_i) / bar(rho) (definition after eq. f0resolved);
+ *   - SGS second moment tau_ij = m^sgs_ij = bar(rho u_i u_j) - rho_bar ut_i ut_j (eq. m_sgs_2);
+ *   - velocity gradient by central differences (App. "Lattice-Boltzmann discretization",
+ *     eqs. fd and strain_rate_discrete);
+ *   - closure expressions: tensor-diffusivity (gradient) model (eq. ansumali), eddy
+ *     viscosity of the Boussinesq row of the FNSE/FRBGK comparison table with the
+ *     Smagorinsky constant of Sec. "Test cases", and the kinetic-closure scalars k_sgs, nu_t,
+ *     omega_t (Sec. "Turbulent relaxation frequency", eqs. ksgs_sharp_trace,
+ *     nu_t_sharp_closure, omega_t_sharp_closure; operational eq. omega_sgs_operational);
+ *   - volume averages of eq. tgv_energy_enstrophy.
+ *
+ * Conventions for every entry point
+ *   Fields are float32, contiguous, structure-of-arrays, x fastest: point (i, j, k) of an
+ *   nx*ny*nz grid is element i + nx*(j + ny*k). A vector field is 3 consecutive blocks
+ *   (x|y|z); a symmetric tensor is 6 blocks in the order xx xy xz yy yz zz; the gradient is
+ *   9 blocks G_ij = d_j ut_i in row-major order (xx xy xz yx yy yz zx zy zz).
+ *   The grid is periodic in all directions with uniform spacing h.
+ *   Field pointers are DEVICE pointers owned by the caller; the library never frees them.
+ *   Structs of parameters and statistics are HOST memory.
+ *   Work is enqueued on the context's HIP stream. Calls that return host statistics
+ *   synchronise that stream before returning; the others are asynchronous.
+ *   Every call returns a kcf_status; no call aborts or throws across the ABI. On failure
+ *   kcf_last_error() gives a message (per thread).
+ */
+#ifndef KCF_H
+#define KCF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KCF_OK = 0,
+  KCF_EINVAL = -1,        /* invalid argument (null pointer, bad size, odd box width, ...) */
+  KCF_ENOMEM = -2,        /* device allocation failed */
+  KCF_EHIP = -3,          /* HIP runtime error */
+  KCF_EUNSUPPORTED = -4,  /* valid request the GPU path does not support (e.g. 2R+1 > n) */
+  KCF_EIO = -5            /* file error (checkpoints) */
+} kcf_status;
+
+typedef enum { KCF_BOX = 0, KCF_GAUSS = 1 } kcf_kind;
+
+typedef struct kcf_ctx kcf_ctx;
+typedef struct kcf_mlp kcf_mlp;
+
+typedef struct { int nx, ny, nz; double h; } kcf_grid;
+
+/* kind: KCF_BOX (delta_over_h even, >= 2) or KCF_GAUSS (delta_over_h >= 1).
+ * precision of the filter sums and of the Favre/tau assembly: 0 = auto (FP64 for widths up
+ * to 4h, where tau is a small difference of large filtered products, FP32 above), 1 = FP32,
+ * 2 = FP64 (radii up to 8). Outputs are float32 in every case. */
+typedef struct { int kind; int delta_over_h; int precision; } kcf_filter;
+
+/* Device output buffers of one filter width; any pointer may be NULL (not produced). */
+typedef struct {
+  float *rho_bar;   /* N   */
+  float *ut;        /* 3N  */
+  float *tau;       /* 6N  */
+  float *grad;      /* 9N  */
+  float *tau_gm;    /* 6N  gradient model */
+  float *tau_smag;  /* 6N  deviatoric eddy-viscosity model */
+  float *k_sgs;     /* N   */
+  float *nu_t;      /* N   */
+  float *omega_t;   /* N   */
+} kcf_outputs;
+
+/* Closure parameters. Pass NULL for the defaults given in brackets. */
+typedef struct {
+  double c_s;        /* Smagorinsky constant [0.11] */
+  double c_nu;       /* kinetic-closure constant C_nu [0.02] */
+  double theta;      /* reference temperature theta (c_s^2 in velocity units) [1] */
+  double nu_mol;     /* molecular viscosity for the clip min(omega, omega_t) [0: none] */
+  double dt;         /* time step of the shifted rate (nu/theta + dt/2)^-1 [0: continuum] */
+  int gm_form;       /* 0: tau_gm = rho_bar C2 G G^T (Taylor) [0]; 1: rho_bar C2 G^T G */
+  int m2_mode;       /* 0: C2 = second moment of the discrete kernel [0]; 1: Delta^2/12 */
+  int ksgs_rho_ref;  /* 0: k_sgs = |tau_kk|/(2 rho_bar) [0]; 1: |tau_kk|/2 (rho0 = 1) */
+} kcf_closure_params;
+
+/* FP64 statistics of one filter width (global reductions on the GPU). */
+typedef struct {
+  double delta, m2;             /* filter width, second moment of the discrete kernel */
+  double mean_rho_bar;          /* <rho_bar> */
+  double ke_resolved;           /* <rho_bar |ut|^2 / 2> */
+  double pi;                    /* SGS dissipation -<tau_ij S_ij> */
+  double pi_gm;                 /* -<tau_gm_ij S_ij> */
+  double pi_smag;               /* -<tau_smag_ij S_ij> */
+  double corr_tau_gm[6];        /* Pearson r(tau_c, tau_gm_c), c = xx xy xz yy yz zz */
+  double corr_pi;               /* Pearson r(-tau:S, -tau_gm:S) over points */
+  double mean_tau[6];
+  int64_t n_points;             /* points counted (finite outputs) */
+  int64_t n_nonfinite;          /* points with a non-finite output (excluded from sums) */
+  double raw[40];               /* the raw FP64 sums the above are derived from */
+} kcf_width_stats;
+
+typedef struct {
+  double mean_rho;              /* <rho> */
+  double ek;                    /* <rho |u|^2 / 2> */
+  double enstrophy;             /* <|curl u|^2 / 2>, sixth-order central differences */
+  int64_t n_nonfinite;
+} kcf_input_summary;
+
+/* ---- library and context ------------------------------------------------------------ */
+int kcf_version(void);  /* 10000 * major + 100 * minor + patch */
+
+/* Create a context on HIP device `device` that enqueues on `stream` (hipStream_t, NULL =
+ * default stream). The context owns only scratch memory for reductions. */
+int kcf_ctx_create(kcf_ctx **out, int device, void *stream);
+int kcf_ctx_set_stream(kcf_ctx *ctx, void *stream);
+void kcf_ctx_destroy(kcf_ctx *ctx);
+const char *kcf_last_error(void);
+
+/* Kernel timing: when enabled, every launch of the filter kernel is bracketed by HIP events
+ * on the context stream; kcf_ctx_kernel_ms returns the summed time of the launches since
+ * the last reset (and the number of launches) after synchronising the stream. */
+int kcf_ctx_enable_timing(kcf_ctx *ctx, int on);
+int kcf_ctx_kernel_ms(kcf_ctx *ctx, double *ms, int *launches);
+
+/* ---- host helper (no GPU) ------------------------------------------------------------ */
+/* 1-D taps w_{-R..R} of the filter used by the GPU (float32), its radius R and the second
+ * moment M2 = sum w_m (m h)^2 computed in double. box: R = n/2, w = 1/n inside and 1/(2n)
+ * at the ends (trapezoidal top-hat of width n h). gauss: exp(-6 m^2/n^2) for |m| <=
+ * ceil(1.5 n), normalised to unit sum. `cap` is the capacity of w (2R+1 needed). */
+int kcf_filter_taps(int kind, int delta_over_h, double h, float *w, int cap, int *radius,
+                    double *m2);
+
+/* ---- the filtering path --------------------------------------------------------------- */
+/* For each of n_filters (1..4) widths, in one pass over rho (N) and u (3N):
+ * products rho, rho u_i, rho u_i u_j; separable periodic filter; Favre division;
+ * tau; central-difference gradient of ut; closures; FP64 statistics.
+ * outs[f] selects the fields written for width f (NULL members are skipped; gradient,
+ * closures and statistics are computed on chip either way). stats may be NULL; when given
+ * it has n_filters entries and the call synchronises the stream.
+ * Errors: KCF_EINVAL for null rho/u/outs/grid, n < 3 in any direction, n_filters outside
+ * 1..4, bad filter kind or width; KCF_EUNSUPPORTED when 2R+1 exceeds a grid dimension or
+ * R > 12. */
+int kcf_filter_favre(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filters,
+                     int n_filters, const float *rho, const float *u, const kcf_outputs *outs,
+                     const kcf_closure_params *cp, kcf_width_stats *stats);
+
+/* Gradient, closures and statistics from stored filtered fields rho_bar (N), ut (3N) and
+ * tau (6N, may be NULL: then k_sgs/nu_t/omega_t and tau statistics are not available and
+ * must not be requested). delta = filter width, m2 = kernel second moment. */
+int kcf_grad_closure(kcf_ctx *ctx, const kcf_grid *grid, const float *rho_bar, const float *ut,
+                     const float *tau, double delta, double m2, const kcf_closure_params *cp,
+                     const kcf_outputs *outs, kcf_width_stats *stats);
+
+/* E_k, enstrophy and <rho> of the unfiltered input (synchronises). */
+int kcf_input_stats(kcf_ctx *ctx, const kcf_grid *grid, const float *rho, const float *u,
+                    kcf_input_summary *out);
+
+/* FP64 sums over the GPU of arbitrary float32 device arrays, for checks of the reduction:
+ * out[0] = sum a, out[1] = sum a^2, out[2] = sum a*b (b may be NULL: then out[2] = 0). */
+int kcf_reduce_check(kcf_ctx *ctx, const float *a, const float *b, int64_t n, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KCF_H */

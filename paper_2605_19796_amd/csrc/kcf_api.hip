@@ -1,0 +1,488 @@
+// C-ABI layer of libkcf: argument checks, filter taps, launch geometry, FP64 statistics.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kcf.h"
+#include "kcf_internal.h"
+
+using namespace kcf;
+
+struct kcf_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  double* d_part = nullptr;   // FP64 partial sums of the kernels
+  size_t part_cap = 0;        // doubles
+  double* d_sums = nullptr;   // reduced sums (device)
+  double* h_sums = nullptr;   // reduced sums (pinned host)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
+  size_t ev_used = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(KCF_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define KCF_HIP(call, what)                      \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+constexpr int kSumCap = 4 * kNStat;
+
+int ensure_partials(kcf_ctx* c, size_t n) {
+  if (n <= c->part_cap) return KCF_OK;
+  if (c->d_part) {
+    hipStreamSynchronize(c->stream);
+    hipFree(c->d_part);
+    c->d_part = nullptr;
+    c->part_cap = 0;
+  }
+  if (hipMalloc(&c->d_part, n * sizeof(double)) != hipSuccess)
+    return fail(KCF_ENOMEM, "cannot allocate FP64 partial sums");
+  c->part_cap = n;
+  return KCF_OK;
+}
+
+int check_grid(const kcf_grid* g) {
+  if (!g) return fail(KCF_EINVAL, "grid is NULL");
+  if (g->nx < 3 || g->ny < 3 || g->nz < 3) return fail(KCF_EINVAL, "grid needs n >= 3 per direction");
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(KCF_EINVAL, "grid spacing must be > 0");
+  if ((int64_t)g->nx * g->ny > (int64_t)1 << 30) return fail(KCF_EUNSUPPORTED, "plane too large");
+  return KCF_OK;
+}
+
+struct Taps {
+  double wd[2 * 64 + 1];
+  int R;
+  double m2;
+};
+
+// Taps in double: box = trapezoidal top-hat of width n h, gauss = exp(-6 m^2/n^2) on
+// |m| <= ceil(1.5 n) normalised to unit sum; M2 = sum w_m (m h)^2.
+int compute_taps(int kind, int n, double h, Taps& t) {
+  if (!(h > 0.0)) return fail(KCF_EINVAL, "grid spacing must be > 0");
+  int R;
+  if (kind == KCF_BOX) {
+    if (n < 2 || (n & 1)) return fail(KCF_EINVAL, "box filter needs an even width >= 2 (in h)");
+    R = n / 2;
+    if (2 * R + 1 > 129) return fail(KCF_EUNSUPPORTED, "filter too wide");
+    for (int m = -R; m <= R; ++m) t.wd[m + R] = (m == -R || m == R) ? 0.5 / n : 1.0 / n;
+  } else if (kind == KCF_GAUSS) {
+    if (n < 1) return fail(KCF_EINVAL, "gaussian filter needs a width >= 1 (in h)");
+    R = (int)std::ceil(1.5 * n);
+    if (2 * R + 1 > 129) return fail(KCF_EUNSUPPORTED, "filter too wide");
+    double s = 0;
+    for (int m = -R; m <= R; ++m) {
+      t.wd[m + R] = std::exp(-6.0 * (double)m * m / ((double)n * n));
+      s += t.wd[m + R];
+    }
+    for (int m = -R; m <= R; ++m) t.wd[m + R] /= s;
+  } else {
+    return fail(KCF_EINVAL, "unknown filter kind");
+  }
+  t.R = R;
+  double mm = 0;
+  for (int m = -R; m <= R; ++m) mm += t.wd[m + R] * (m * h) * (m * h);
+  t.m2 = mm;
+  return KCF_OK;
+}
+
+void set_closure(WidthArgs& W, const kcf_closure_params* cp, double delta, double m2) {
+  kcf_closure_params d{0.11, 0.02, 1.0, 0.0, 0.0, 0, 0, 0};
+  if (cp) d = *cp;
+  W.gm_coef = (float)(d.m2_mode == 1 ? delta * delta / 12.0 : m2);
+  W.smag_coef = (float)((d.c_s * delta) * (d.c_s * delta));
+  W.cnu_delta = (float)(d.c_nu * delta);
+  W.inv_theta = (float)(1.0 / d.theta);
+  W.nu_mol = (float)d.nu_mol;
+  W.half_dt = (float)(0.5 * d.dt);
+  W.gm_form = d.gm_form;
+  W.ksgs_rho_ref = d.ksgs_rho_ref;
+}
+
+int check_closure(const kcf_closure_params* cp) {
+  if (!cp) return KCF_OK;
+  if (!(cp->theta > 0)) return fail(KCF_EINVAL, "theta must be > 0");
+  if (cp->nu_mol < 0 || cp->dt < 0 || cp->c_s < 0 || cp->c_nu < 0)
+    return fail(KCF_EINVAL, "closure constants must be >= 0");
+  if ((cp->gm_form != 0 && cp->gm_form != 1) || (cp->m2_mode != 0 && cp->m2_mode != 1) ||
+      (cp->ksgs_rho_ref != 0 && cp->ksgs_rho_ref != 1))
+    return fail(KCF_EINVAL, "closure flags must be 0 or 1");
+  return KCF_OK;
+}
+
+void set_outputs(WidthArgs& W, const kcf_outputs* o) {
+  W.rho_bar = o->rho_bar;
+  W.ut = o->ut;
+  W.tau = o->tau;
+  W.grad = o->grad;
+  W.tau_gm = o->tau_gm;
+  W.tau_smag = o->tau_smag;
+  W.k_sgs = o->k_sgs;
+  W.nu_t = o->nu_t;
+  W.omega_t = o->omega_t;
+}
+
+// Statistics of one width from its 40 FP64 sums.
+void derive_stats(const double* raw, double delta, double m2, kcf_width_stats* s) {
+  std::memset(s, 0, sizeof(*s));
+  std::memcpy(s->raw, raw, sizeof(double) * kNStat);
+  s->delta = delta;
+  s->m2 = m2;
+  const double n = raw[S_N];
+  s->n_points = (int64_t)llround(n);
+  s->n_nonfinite = (int64_t)llround(raw[S_NONFINITE]);
+  if (n <= 0) return;
+  s->mean_rho_bar = raw[S_RHO] / n;
+  s->ke_resolved = raw[S_KE] / n;
+  s->pi = raw[S_PI] / n;
+  s->pi_gm = raw[S_PIGM] / n;
+  s->pi_smag = raw[S_PISM] / n;
+  auto corr = [n](double sa, double sb, double saa, double sbb, double sab) {
+    const double cov = sab - sa * sb / n;
+    const double va = saa - sa * sa / n;
+    const double vb = sbb - sb * sb / n;
+    return (va > 0 && vb > 0) ? cov / std::sqrt(va * vb) : NAN;
+  };
+  for (int c = 0; c < 6; ++c) {
+    s->mean_tau[c] = raw[S_TAU + c] / n;
+    s->corr_tau_gm[c] = corr(raw[S_TAU + c], raw[S_TGM + c], raw[S_TAU2 + c], raw[S_TGM2 + c],
+                             raw[S_TAUTGM + c]);
+  }
+  s->corr_pi = corr(raw[S_PI], raw[S_PIGM], raw[S_PI2], raw[S_PIGM2], raw[S_PIPIGM]);
+}
+
+int reduce_to_host(kcf_ctx* c, int nparts, int nstat, int slot) {
+  hipError_t e = launch_reduce(c->d_part, nparts, nstat, c->d_sums + slot * kNStat, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  return KCF_OK;
+}
+
+int timed_begin(kcf_ctx* c) {
+  if (!c->timing) return KCF_OK;
+  if (c->ev_used + 2 > c->ev.size()) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      KCF_HIP(hipEventCreate(&e), "hipEventCreate");
+      c->ev.push_back(e);
+    }
+  }
+  KCF_HIP(hipEventRecord(c->ev[c->ev_used], c->stream), "hipEventRecord");
+  return KCF_OK;
+}
+
+int timed_end(kcf_ctx* c) {
+  if (!c->timing) return KCF_OK;
+  KCF_HIP(hipEventRecord(c->ev[c->ev_used + 1], c->stream), "hipEventRecord");
+  c->ev_used += 2;
+  return KCF_OK;
+}
+
+// Number of z chunks: enough workgroups to fill the chip, balanced against the 2R+2 planes
+// each chunk spends filling its ring.
+int choose_zchunks(int64_t items_per_chunk, int nz, int R) {
+  const double cus = 256.0;
+  double best = -1;
+  int best_n = 1;
+  for (int n = 1; n <= 16; ++n) {
+    const int zlen = (nz + n - 1) / n;
+    if (zlen < 4) break;
+    const double blocks = (double)items_per_chunk * n;
+    const double rounds = std::ceil(blocks / cus);
+    const double fill = blocks / (rounds * cus);
+    const double eff = fill * zlen / (double)(zlen + 2 * R + 2);
+    if (eff > best + 1e-9) {
+      best = eff;
+      best_n = n;
+    }
+  }
+  return best_n;
+}
+
+}  // namespace
+
+extern "C" {
+
+int kcf_version(void) { return 100; }
+
+const char* kcf_last_error(void) { return g_err.c_str(); }
+
+int kcf_ctx_create(kcf_ctx** out, int device, void* stream) {
+  if (!out) return fail(KCF_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  KCF_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(KCF_EINVAL, "no such device");
+  KCF_HIP(hipSetDevice(device), "hipSetDevice");
+  kcf_ctx* c = new kcf_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  if (hipMalloc(&c->d_sums, kSumCap * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&c->h_sums, kSumCap * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    kcf_ctx_destroy(c);
+    return fail(KCF_ENOMEM, "cannot allocate statistics buffers");
+  }
+  *out = c;
+  return KCF_OK;
+}
+
+int kcf_ctx_set_stream(kcf_ctx* c, void* stream) {
+  if (!c) return fail(KCF_EINVAL, "ctx is NULL");
+  c->stream = (hipStream_t)stream;
+  return KCF_OK;
+}
+
+void kcf_ctx_destroy(kcf_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  if (c->d_part) hipFree(c->d_part);
+  if (c->d_sums) hipFree(c->d_sums);
+  if (c->h_sums) hipHostFree(c->h_sums);
+  for (hipEvent_t e : c->ev) hipEventDestroy(e);
+  delete c;
+}
+
+int kcf_ctx_enable_timing(kcf_ctx* c, int on) {
+  if (!c) return fail(KCF_EINVAL, "ctx is NULL");
+  c->timing = on != 0;
+  c->ev_used = 0;
+  return KCF_OK;
+}
+
+int kcf_ctx_kernel_ms(kcf_ctx* c, double* ms, int* launches) {
+  if (!c || !ms) return fail(KCF_EINVAL, "NULL argument");
+  KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  double t = 0;
+  for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+    float m = 0;
+    KCF_HIP(hipEventElapsedTime(&m, c->ev[i], c->ev[i + 1]), "hipEventElapsedTime");
+    t += m;
+  }
+  *ms = t;
+  if (launches) *launches = (int)(c->ev_used / 2);
+  c->ev_used = 0;
+  return KCF_OK;
+}
+
+int kcf_filter_taps(int kind, int n, double h, float* w, int cap, int* radius, double* m2) {
+  if (!w || !radius) return fail(KCF_EINVAL, "NULL argument");
+  Taps t;
+  int rc = compute_taps(kind, n, h, t);
+  if (rc) return rc;
+  *radius = t.R;
+  if (2 * t.R + 1 > cap) return fail(KCF_EINVAL, "tap buffer too small");
+  for (int m = 0; m < 2 * t.R + 1; ++m) w[m] = (float)t.wd[m];
+  if (m2) *m2 = t.m2;
+  return KCF_OK;
+}
+
+int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters, int nf,
+                     const float* rho, const float* u, const kcf_outputs* outs,
+                     const kcf_closure_params* cp, kcf_width_stats* stats) {
+  if (!c) return fail(KCF_EINVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!filters || !outs || !rho || !u) return fail(KCF_EINVAL, "NULL argument");
+  if (nf < 1 || nf > 4) return fail(KCF_EINVAL, "n_filters must be 1..4");
+  if ((rc = check_closure(cp))) return rc;
+  Taps taps[4];
+  int radii[4], kr[4], fp64[4];
+  for (int f = 0; f < nf; ++f) {
+    if ((rc = compute_taps(filters[f].kind, filters[f].delta_over_h, grid->h, taps[f]))) return rc;
+    radii[f] = taps[f].R;
+    if (taps[f].R > kMaxR) return fail(KCF_EUNSUPPORTED, "filter radius above 12 cells");
+    const int nmin = std::min(grid->nx, std::min(grid->ny, grid->nz));
+    if (2 * taps[f].R + 1 > nmin)
+      return fail(KCF_EUNSUPPORTED, "filter support 2R+1 exceeds the grid");
+    kr[f] = kernel_radius_for(taps[f].R);
+    const int p = filters[f].precision;
+    if (p < 0 || p > 2) return fail(KCF_EINVAL, "precision must be 0 (auto), 1 (fp32) or 2 (fp64)");
+    fp64[f] = p == 2 || (p == 0 && filters[f].delta_over_h <= 4);
+    if (fp64[f] && !fp64_supported(kr[f]))
+      return fail(KCF_EUNSUPPORTED, "FP64 accumulation is limited to radii <= 8");
+  }
+  KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  FilterArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.rho = rho;
+  A.u = u;
+  A.nx = grid->nx;
+  A.ny = grid->ny;
+  A.nz = grid->nz;
+  A.ntot = (int64_t)grid->nx * grid->ny * grid->nz;
+  A.inv2h = (float)(1.0 / (2.0 * grid->h));
+  A.ntx = (grid->nx + kOX - 1) / kOX;
+  A.nty = (grid->ny + kOY - 1) / kOY;
+  A.ntiles = A.ntx * A.nty;
+
+  const bool fused = nf == 4 && radii[0] == 1 && radii[1] == 2 && radii[2] == 4 &&
+                     radii[3] == 8 && fp64[0] && fp64[1] && !fp64[2] && !fp64[3];
+  const int rmax = fused ? 8 : 0;
+  // z chunks: one decision for the whole call
+  int rr = 0;
+  for (int f = 0; f < nf; ++f) rr = std::max(rr, kr[f]);
+  (void)rmax;
+  A.nzc = choose_zchunks((int64_t)A.ntiles * (fused ? 4 : 1), grid->nz, rr);
+  A.zlen = (grid->nz + A.nzc - 1) / A.nzc;
+  A.nzc = (grid->nz + A.zlen - 1) / A.zlen;
+  const int items = A.ntiles * A.nzc;
+  A.tiles_per_xcd = (items + 7) / 8;
+  const size_t per_width = (size_t)items * kStatWaves * kNStat;
+  if ((rc = ensure_partials(c, per_width * nf))) return rc;
+
+  for (int f = 0; f < nf; ++f) {
+    WidthArgs& W = A.wa[fused ? f : 0];
+    std::memset(&W, 0, sizeof(W));
+    const int R = taps[f].R, K = fused ? radii[f] : kr[f];
+    for (int m = 0; m < 2 * K + 1; ++m) {
+      const int mm = m - (K - R);
+      W.wd[m] = (mm >= 0 && mm < 2 * R + 1) ? taps[f].wd[mm] : 0.0;
+      W.w[m] = (float)W.wd[m];
+    }
+    set_outputs(W, &outs[f]);
+    set_closure(W, cp, filters[f].delta_over_h * grid->h, taps[f].m2);
+    W.partials = c->d_part + per_width * f;
+    if (!fused) {
+      A.nw = 1;
+      if ((rc = timed_begin(c))) return rc;
+      hipError_t e = launch_filter(A, &kr[f], &fp64[f], 8 * A.tiles_per_xcd, c->stream);
+      if (e != hipSuccess) return hip_fail(e, "filter launch");
+      if ((rc = timed_end(c))) return rc;
+    }
+  }
+  if (fused) {
+    A.nw = 4;
+    if ((rc = timed_begin(c))) return rc;
+    hipError_t e = launch_filter(A, kr, fp64, 8 * 4 * A.tiles_per_xcd, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "filter launch");
+    if ((rc = timed_end(c))) return rc;
+  }
+  if (stats) {
+    for (int f = 0; f < nf; ++f) {
+      hipError_t e = launch_reduce(c->d_part + per_width * f, items * kStatWaves, kNStat,
+                                   c->d_sums + f * kNStat, c->stream);
+      if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    }
+    KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * kNStat * nf,
+                           hipMemcpyDeviceToHost, c->stream), "stats copy");
+    KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    for (int f = 0; f < nf; ++f)
+      derive_stats(c->h_sums + f * kNStat, filters[f].delta_over_h * grid->h, taps[f].m2,
+                   &stats[f]);
+  }
+  return KCF_OK;
+}
+
+int kcf_grad_closure(kcf_ctx* c, const kcf_grid* grid, const float* rho_bar, const float* ut,
+                     const float* tau, double delta, double m2, const kcf_closure_params* cp,
+                     const kcf_outputs* outs, kcf_width_stats* stats) {
+  if (!c) return fail(KCF_EINVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!rho_bar || !ut || !outs) return fail(KCF_EINVAL, "NULL argument");
+  if (!(delta > 0) || !(m2 >= 0)) return fail(KCF_EINVAL, "delta must be > 0 and m2 >= 0");
+  if ((rc = check_closure(cp))) return rc;
+  if (!tau && (outs->k_sgs || outs->nu_t || outs->omega_t || stats))
+    return fail(KCF_EINVAL, "k_sgs, nu_t, omega_t and statistics need tau");
+  KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  ClosureArgs C;
+  std::memset(&C, 0, sizeof(C));
+  C.rho_bar = rho_bar;
+  C.ut = ut;
+  C.tau = tau;
+  C.nx = grid->nx;
+  C.ny = grid->ny;
+  C.nz = grid->nz;
+  C.ntot = (int64_t)grid->nx * grid->ny * grid->nz;
+  C.inv2h = (float)(1.0 / (2.0 * grid->h));
+  set_outputs(C.wa, outs);
+  set_closure(C.wa, cp, delta, m2);
+  const int nb = grad_closure_blocks(C.ntot);
+  if (stats) {
+    if ((rc = ensure_partials(c, (size_t)nb * 4 * kNStat))) return rc;
+    C.wa.partials = c->d_part;
+  }
+  int nb2 = 0;
+  hipError_t e = launch_grad_closure(C, &nb2, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "closure launch");
+  if (stats) {
+    if ((rc = reduce_to_host(c, nb * 4, kNStat, 0))) return rc;
+    KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * kNStat, hipMemcpyDeviceToHost,
+                           c->stream), "stats copy");
+    KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    derive_stats(c->h_sums, delta, m2, stats);
+  }
+  return KCF_OK;
+}
+
+int kcf_input_stats(kcf_ctx* c, const kcf_grid* grid, const float* rho, const float* u,
+                    kcf_input_summary* out) {
+  if (!c) return fail(KCF_EINVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!rho || !u || !out) return fail(KCF_EINVAL, "NULL argument");
+  if (grid->nx < 7 || grid->ny < 7 || grid->nz < 7)
+    return fail(KCF_EUNSUPPORTED, "sixth-order vorticity needs n >= 7");
+  KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  InputStatArgs S;
+  S.rho = rho;
+  S.u = u;
+  S.nx = grid->nx;
+  S.ny = grid->ny;
+  S.nz = grid->nz;
+  S.ntot = (int64_t)grid->nx * grid->ny * grid->nz;
+  S.inv60h = 1.0 / (60.0 * grid->h);
+  int64_t nb = (S.ntot + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  if ((rc = ensure_partials(c, (size_t)nb * 4 * 4))) return rc;
+  S.partials = c->d_part;
+  hipError_t e = launch_input_stats(S, (int)nb, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "input stats launch");
+  e = launch_reduce(c->d_part, (int)nb * 4, 4, c->d_sums, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * 4, hipMemcpyDeviceToHost,
+                         c->stream), "stats copy");
+  KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  const double n = (double)S.ntot - c->h_sums[3];
+  out->mean_rho = c->h_sums[0] / n;
+  out->ek = c->h_sums[1] / n;
+  out->enstrophy = c->h_sums[2] / n;
+  out->n_nonfinite = (int64_t)llround(c->h_sums[3]);
+  return KCF_OK;
+}
+
+int kcf_reduce_check(kcf_ctx* c, const float* a, const float* b, int64_t n, double* out) {
+  if (!c || !a || !out) return fail(KCF_EINVAL, "NULL argument");
+  if (n < 1) return fail(KCF_EINVAL, "n must be >= 1");
+  KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  int64_t nb = (n + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  int rc = ensure_partials(c, (size_t)nb * 4 * 3);
+  if (rc) return rc;
+  hipError_t e = launch_reduce_check(a, b, n, c->d_part, (int)nb, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  e = launch_reduce(c->d_part, (int)nb * 4, 3, c->d_sums, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * 3, hipMemcpyDeviceToHost,
+                         c->stream), "copy");
+  KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  std::memcpy(out, c->h_sums, sizeof(double) * 3);
+  return KCF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Internal declarations shared by the HIP kernels and the C-ABI layer of libkcf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kcf {
+
+constexpr int kMaxR = 12;                 // largest stencil radius on the GPU
+constexpr int kMaxTaps = 2 * kMaxR + 1;
+constexpr int kNStat = 40;                // FP64 sums per filter width
+constexpr int kCX = 18, kCY = 14;         // computed columns of a tile (1-cell FD halo)
+constexpr int kOX = kCX - 2, kOY = kCY - 2;  // output columns of a tile
+constexpr int kNCol = kCX * kCY;          // 252 columns, two threads each
+constexpr int kNT = 2 * kNCol;            // 504 threads per workgroup (8 waves)
+constexpr int kStatWaves = (kNCol + 63) / 64;  // waves holding the column owners (4)
+constexpr int kYP = kCY / 2;              // rows per task of the y pass
+
+// Slots of the per-width FP64 sums.
+enum StatSlot {
+  S_N = 0, S_RHO = 1, S_KE = 2, S_PI = 3, S_PIGM = 4, S_PI2 = 5, S_PIGM2 = 6, S_PIPIGM = 7,
+  S_TAU = 8, S_TGM = 14, S_TAU2 = 20, S_TGM2 = 26, S_TAUTGM = 32, S_NONFINITE = 38,
+  S_PISM = 39
+};
+
+struct WidthArgs {
+  float w[kMaxTaps];      // taps w_{-R..R} of this width, zero padded to the kernel radius
+  double wd[kMaxTaps];    // the same taps in double (FP64 accumulation)
+  float* rho_bar;
+  float* ut;
+  float* tau;
+  float* grad;
+  float* tau_gm;
+  float* tau_smag;
+  float* k_sgs;
+  float* nu_t;
+  float* omega_t;
+  float gm_coef;          // C2 of the gradient model
+  float smag_coef;        // (C_s Delta)^2
+  float cnu_delta;        // C_nu Delta
+  float inv_theta;        // 1 / theta
+  float nu_mol;           // molecular viscosity of the clip
+  float half_dt;          // dt / 2 of the shifted rate
+  int gm_form;            // 0: G G^T, 1: G^T G
+  int ksgs_rho_ref;       // 0: rho_bar, 1: 1
+  double* partials;       // [blocks][kStatWaves][kNStat] FP64 partial sums
+};
+
+struct FilterArgs {
+  const float* rho;
+  const float* u;
+  int nx, ny, nz;
+  int64_t ntot;
+  float inv2h;
+  int ntx, nty, ntiles;   // output tiles in x, y and their product
+  int nzc, zlen;          // z chunks per column and their length
+  int tiles_per_xcd;      // tiles of one XCD's contiguous band
+  int nw;                 // widths in this launch
+  WidthArgs wa[4];
+};
+
+struct ClosureArgs {        // standalone gradient/closure pass from stored fields
+  const float* rho_bar;
+  const float* ut;
+  const float* tau;
+  int nx, ny, nz;
+  int64_t ntot;
+  float inv2h;
+  WidthArgs wa;
+};
+
+struct InputStatArgs {
+  const float* rho;
+  const float* u;
+  int nx, ny, nz;
+  int64_t ntot;
+  double inv60h;
+  double* partials;       // [blocks][4]
+};
+
+// launchers (kcf_filter.hip)
+hipError_t launch_filter(const FilterArgs& a, const int* radii, const int* fp64, int nblocks,
+                         hipStream_t s);
+bool fp64_supported(int kernel_radius);
+hipError_t launch_grad_closure(const ClosureArgs& a, int* nblocks, hipStream_t s);
+int grad_closure_blocks(int64_t ntot);
+hipError_t launch_input_stats(const InputStatArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_reduce(const double* partials, int nparts, int nstat, double* out,
+                         hipStream_t s);
+hipError_t launch_reduce_check(const float* a, const float* b, int64_t n, double* partials,
+                               int nblocks, hipStream_t s);
+int kernel_radius_for(int r);   // radius of the kernel instance used for stencil radius r
+
+}  // namespace kcf

@@ -1,0 +1,228 @@
+"""ctypes binding of libkcf (argument marshalling only; every step runs in the HIP library).
+
+Tensors are torch CUDA (ROCm) tensors used as device buffers; the context enqueues on the
+current torch stream unless another stream is given. The library file is the in-tree
+``libkcf.so`` built by ``paper_2605_19796_amd.build``; importing this module does not load
+it, ``lib()`` does and raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libkcf.so")
+
+BOX, GAUSS = 0, 1
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, EIO = 0, -1, -2, -3, -4, -5
+
+
+class KcfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"kcf error {code}: {msg}")
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("h", C.c_double)]
+
+
+class Filter(C.Structure):
+    _fields_ = [("kind", C.c_int), ("delta_over_h", C.c_int), ("precision", C.c_int)]
+
+
+class Outputs(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in
+                ("rho_bar", "ut", "tau", "grad", "tau_gm", "tau_smag", "k_sgs", "nu_t", "omega_t")]
+
+
+class ClosureParams(C.Structure):
+    _fields_ = [("c_s", C.c_double), ("c_nu", C.c_double), ("theta", C.c_double),
+                ("nu_mol", C.c_double), ("dt", C.c_double), ("gm_form", C.c_int),
+                ("m2_mode", C.c_int), ("ksgs_rho_ref", C.c_int)]
+
+
+class WidthStats(C.Structure):
+    _fields_ = [("delta", C.c_double), ("m2", C.c_double), ("mean_rho_bar", C.c_double),
+                ("ke_resolved", C.c_double), ("pi", C.c_double), ("pi_gm", C.c_double),
+                ("pi_smag", C.c_double), ("corr_tau_gm", C.c_double * 6), ("corr_pi", C.c_double),
+                ("mean_tau", C.c_double * 6), ("n_points", C.c_int64), ("n_nonfinite", C.c_int64),
+                ("raw", C.c_double * 40)]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if hasattr(v, "__len__") else v
+        return d
+
+
+class InputSummary(C.Structure):
+    _fields_ = [("mean_rho", C.c_double), ("ek", C.c_double), ("enstrophy", C.c_double),
+                ("n_nonfinite", C.c_int64)]
+
+
+# exported symbol -> (restype, argtypes)
+_SIGS = {
+    "kcf_version": (C.c_int, []),
+    "kcf_last_error": (C.c_char_p, []),
+    "kcf_ctx_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    "kcf_ctx_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "kcf_ctx_destroy": (None, [C.c_void_p]),
+    "kcf_ctx_enable_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "kcf_ctx_kernel_ms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "kcf_filter_taps": (C.c_int, [C.c_int, C.c_int, C.c_double, C.POINTER(C.c_float), C.c_int,
+                                  C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "kcf_filter_favre": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.POINTER(Filter), C.c_int,
+                                   C.c_void_p, C.c_void_p, C.POINTER(Outputs),
+                                   C.POINTER(ClosureParams), C.POINTER(WidthStats)]),
+    "kcf_grad_closure": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_double, C.c_double, C.POINTER(ClosureParams),
+                                   C.POINTER(Outputs), C.POINTER(WidthStats)]),
+    "kcf_input_stats": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p,
+                                  C.POINTER(InputSummary)]),
+    "kcf_reduce_check": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                   C.POINTER(C.c_double)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libkcf.so (in-tree). Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run python -m paper_2605_19796_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def check(rc):
+    if rc != OK:
+        raise KcfError(rc, lib().kcf_last_error().decode())
+    return rc
+
+
+def filter_taps(kind, delta_over_h, h):
+    """Host-side taps of the GPU filter: (float32 list w, radius R, second moment M2)."""
+    buf = (C.c_float * 129)()
+    R = C.c_int()
+    m2 = C.c_double()
+    check(lib().kcf_filter_taps(kind, delta_over_h, h, buf, 129, C.byref(R), C.byref(m2)))
+    return [buf[i] for i in range(2 * R.value + 1)], R.value, m2.value
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    import torch
+    if t.dtype != torch.float32:
+        raise ValueError("expected float32")
+    return C.c_void_p(t.data_ptr())
+
+
+def params(c_s=0.11, c_nu=0.02, theta=1.0, nu_mol=0.0, dt=0.0, gm_form=0, m2_mode=0,
+           ksgs_rho_ref=0):
+    return ClosureParams(c_s, c_nu, theta, nu_mol, dt, gm_form, m2_mode, ksgs_rho_ref)
+
+
+OUT_SIZES = dict(rho_bar=1, ut=3, tau=6, grad=9, tau_gm=6, tau_smag=6, k_sgs=1, nu_t=1, omega_t=1)
+
+
+def alloc_outputs(shape, device, fields=("rho_bar", "ut", "tau", "grad", "tau_gm")):
+    """Device tensors for the requested outputs: dict name -> tensor (comp, nz, ny, nx)."""
+    import torch
+    nz, ny, nx = shape
+    return {f: torch.empty((OUT_SIZES[f], nz, ny, nx), dtype=torch.float32, device=device)
+            for f in fields}
+
+
+def _outputs_struct(d):
+    o = Outputs()
+    for name in OUT_SIZES:
+        t = d.get(name) if d else None
+        setattr(o, name, _ptr(t).value if t is not None else None)
+    return o
+
+
+class Context:
+    """A libkcf context bound to one device and stream."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self._lib = lib()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        check(self._lib.kcf_ctx_create(C.byref(h), device, C.c_void_p(stream.cuda_stream)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            self._lib.kcf_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def enable_timing(self, on=True):
+        check(self._lib.kcf_ctx_enable_timing(self.handle, 1 if on else 0))
+
+    def kernel_ms(self):
+        ms = C.c_double()
+        n = C.c_int()
+        check(self._lib.kcf_ctx_kernel_ms(self.handle, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def filter_favre(self, rho, u, h, filters, outs, cp=None, stats=True):
+        """rho (nz,ny,nx), u (3,nz,ny,nx) device float32; filters: list of (kind, n[, precision]);
+        outs: list (one per filter) of dicts name -> tensor. Returns list of stats dicts."""
+        nz, ny, nx = rho.shape
+        g = Grid(nx, ny, nz, h)
+        nf = len(filters)
+        fa = (Filter * nf)(*[Filter(*f) if len(f) == 3 else Filter(f[0], f[1], 0) for f in filters])
+        oa = (Outputs * nf)(*[_outputs_struct(o) for o in outs])
+        st = (WidthStats * nf)() if stats else None
+        check(self._lib.kcf_filter_favre(self.handle, C.byref(g), fa, nf, _ptr(rho), _ptr(u), oa,
+                                         C.byref(cp) if cp is not None else None, st))
+        return [s.as_dict() for s in st] if stats else None
+
+    def grad_closure(self, rho_bar, ut, tau, h, delta, m2, outs, cp=None, stats=True):
+        nz, ny, nx = rho_bar.shape[-3:]
+        g = Grid(nx, ny, nz, h)
+        o = _outputs_struct(outs)
+        st = WidthStats() if stats else None
+        check(self._lib.kcf_grad_closure(self.handle, C.byref(g), _ptr(rho_bar), _ptr(ut), _ptr(tau),
+                                         delta, m2, C.byref(cp) if cp is not None else None,
+                                         C.byref(o), C.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def input_stats(self, rho, u, h):
+        nz, ny, nx = rho.shape
+        g = Grid(nx, ny, nz, h)
+        s = InputSummary()
+        check(self._lib.kcf_input_stats(self.handle, C.byref(g), _ptr(rho), _ptr(u), C.byref(s)))
+        return dict(mean_rho=s.mean_rho, ek=s.ek, enstrophy=s.enstrophy, n_nonfinite=s.n_nonfinite)
+
+    def reduce_check(self, a, b=None):
+        out = (C.c_double * 3)()
+        check(self._lib.kcf_reduce_check(self.handle, _ptr(a), _ptr(b), a.numel(), out))
+        return list(out)

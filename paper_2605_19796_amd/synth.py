@@ -17,7 +17,8 @@ Spectral recipe (random-phase solenoidal field):
   the plane normal to k (divergence free); k = 0 and the Nyquist planes are zeroed;
   an inverse real FFT gives the field, which is rescaled to an exact rms magnitude
   sqrt(<u_i u_i>) = urms.  The density is 1 + amp * s, where s has the same spectrum,
-  zero mean and unit rms.
+  zero mean and unit peak amplitude (max |s| = 1), so rho stays in [1 - amp, 1 + amp]
+  at every grid size (a unit-rms Gaussian scalar would reach 5-6 sigma on 10^7 points).
 """
 from __future__ import annotations
 
@@ -75,14 +76,14 @@ def spectral_velocity(n: int, k0: float, urms: float, seed: int, device="cpu") -
 
 
 def spectral_scalar(n: int, k0: float, seed: int, device="cpu") -> torch.Tensor:
-    """Zero-mean, unit-rms random-phase scalar with the velocity's spectrum, (n, n, n) float64."""
+    """Zero-mean random-phase scalar with the velocity's spectrum and max |s| = 1, float64."""
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
     _, _, _, _, amp = _spectral_amplitude(n, k0, device)
     c = _complex_normal((n, n, n // 2 + 1), gen, device) * amp
     s = torch.fft.irfftn(c, s=(n, n, n), dim=(0, 1, 2))
     s = s - s.mean()
-    s = s / torch.sqrt((s * s).mean())
+    s = s / s.abs().max()
     return s
 
 

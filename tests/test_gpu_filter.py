@@ -1,0 +1,342 @@
+"""GPU parity of the filtering path against the FP64 oracle, through the C ABI.
+
+Tolerance (floating point): per output component c,
+    max_x |gpu_c - oracle_c| / max_x |oracle_c| <= 1e-5
+on the same float32 inputs. Statistics: GPU FP64 reductions of the GPU's own fields agree
+with host FP64 sums of those fields to 1e-10 relative; against the oracle's statistics
+they agree to the field tolerance.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+from oracle import fields as F  # noqa: E402
+from paper_2605_19796_amd import kcf, synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+ALL = ("rho_bar", "ut", "tau", "grad", "tau_gm", "tau_smag", "k_sgs", "nu_t", "omega_t")
+PAIRS = F.PAIRS
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = kcf.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def rel(g, o):
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    m = np.max(np.abs(o))
+    return float(np.max(np.abs(g - o)) / m) if m > 0 else float(np.max(np.abs(g)))
+
+
+def oracle_as_gpu_layout(o):
+    """Oracle full-path dict -> arrays laid out like the GPU outputs."""
+    sym = lambda t: np.stack([t[i, j] for (i, j) in PAIRS])
+    return dict(rho_bar=o["rho_bar"][None], ut=o["ut"], tau=sym(o["tau"]),
+                grad=o["G"].reshape((9,) + o["G"].shape[2:]), tau_gm=sym(o["tau_gm"]),
+                tau_smag=sym(o["tau_smag"]), k_sgs=o["k_sgs"][None], nu_t=o["nu_t"][None],
+                omega_t=o["omega_t"][None])
+
+
+def run_gpu(ctx, rho, u, h, filters, fields=ALL, cp=None):
+    r = dev(rho)
+    uu = dev(u)
+    outs = [kcf.alloc_outputs(rho.shape, "cuda", fields) for _ in filters]
+    for o in outs:
+        for t in o.values():
+            t.fill_(float("nan"))
+    st = ctx.filter_favre(r, uu, h, filters, outs, cp=cp)
+    torch.cuda.synchronize()
+    return [{k: v.cpu().numpy() for k, v in o.items()} for o in outs], st
+
+
+def check_fields(gpu, ora, tol=TOL, fields=ALL):
+    errs = {}
+    for f in fields:
+        for c in range(gpu[f].shape[0]):
+            e = rel(gpu[f][c], ora[f][c])
+            errs[f"{f}[{c}]"] = e
+    worst = max(errs, key=errs.get)
+    assert errs[worst] <= tol, f"{worst}: {errs[worst]:.3g} (all: {errs})"
+    return errs
+
+
+def check_stats(st, o, tol=1e-5):
+    os_ = o["stats"]
+    assert st["n_nonfinite"] == 0
+    assert abs(st["mean_rho_bar"] - os_["mean_rho_bar"]) <= 1e-6 * abs(os_["mean_rho_bar"])
+    assert abs(st["ke_resolved"] - os_["ke_resolved"]) <= tol * abs(os_["ke_resolved"])
+    assert abs(st["pi"] - os_["pi"]) <= tol * abs(os_["pi"]) + 1e-12
+    assert abs(st["pi_gm"] - os_["pi_gm"]) <= tol * abs(os_["pi_gm"]) + 1e-12
+    for c in range(6):
+        assert abs(st["corr_tau_gm"][c] - os_["corr_tau_gm"][c]) <= 1e-4, (c, st["corr_tau_gm"], os_["corr_tau_gm"])
+    assert abs(st["corr_pi"] - os_["corr_pi"]) <= 1e-4
+
+
+# ------------------------------------------------------------------ small full-field parity
+CASES = [
+    ("c32_box4", (32, 32, 32), F.BOX, 4),
+    ("ragged_box2", (20, 26, 35), F.BOX, 2),
+    ("ragged_gauss2", (19, 17, 23), F.GAUSS, 2),
+    ("small8_box4", (8, 8, 8), F.BOX, 4),
+    ("ragged_box8", (21, 30, 37), F.BOX, 8),
+    ("gauss4_40", (40, 36, 33), F.GAUSS, 4),
+]
+
+
+@pytest.mark.parametrize("name,shape,kind,nd", CASES)
+def test_full_field_parity(ctx, name, shape, kind, nd):
+    say(f"[gpu] full-field parity {name} shape={shape} kind={kind} n={nd}")
+    if name == "c32_box4":
+        rho, u = synth.workload_fields("c32_box4")
+        rho, u = rho.numpy(), u.numpy()
+        h = 2 * math.pi / 32
+    else:
+        rho, u = synth.random_fields(shape, seed=hash(name) % 1000)
+        h = 0.1
+    gpu, st = run_gpu(ctx, rho, u, h, [(kind, nd)])
+    ora = F.full_path(rho, u, kind, nd, h)
+    check_fields(gpu[0], oracle_as_gpu_layout(ora))
+    check_stats(st[0], ora)
+
+
+def test_gauss8_full_field_64(ctx):
+    say("[gpu] gaussian delta=8h (R=12) full field 64^3")
+    rho, u = synth.workload_fields("c256_gauss8", n=64)
+    rho, u = rho.numpy(), u.numpy()
+    h = 2 * math.pi / 64
+    gpu, st = run_gpu(ctx, rho, u, h, [(F.GAUSS, 8)])
+    ora = F.full_path(rho, u, F.GAUSS, 8, h)
+    check_fields(gpu[0], oracle_as_gpu_layout(ora))
+    check_stats(st[0], ora)
+
+
+def test_multiwidth_fused_matches_single_and_oracle(ctx):
+    say("[gpu] fused box widths 2,4,8,16 at 40^3")
+    rho, u = synth.workload_fields("c512_box_multi", n=40)
+    rho, u = rho.numpy(), u.numpy()
+    h = 2 * math.pi / 40
+    filters = [(F.BOX, 2), (F.BOX, 4), (F.BOX, 8), (F.BOX, 16)]
+    gpu, st = run_gpu(ctx, rho, u, h, filters)
+    for i, (kind, nd) in enumerate(filters):
+        ora = F.full_path(rho, u, kind, nd, h)
+        check_fields(gpu[i], oracle_as_gpu_layout(ora))
+        check_stats(st[i], ora)
+        single, st1 = run_gpu(ctx, rho, u, h, [(kind, nd)])
+        for f in ALL:
+            d = rel(gpu[i][f], single[0][f])
+            assert d <= 1e-6, (nd, f, d)
+
+
+@pytest.mark.parametrize("cp", [dict(gm_form=1), dict(m2_mode=1), dict(ksgs_rho_ref=1),
+                                dict(nu_mol=0.002, theta=1.0 / 3.0, dt=1.0, c_s=0.105, c_nu=0.035)])
+def test_closure_variants(ctx, cp):
+    say(f"[gpu] closure variant {cp}")
+    rho, u = synth.random_fields((16, 18, 20), seed=3)
+    h = 0.2
+    gpu, _ = run_gpu(ctx, rho, u, h, [(F.BOX, 4)], cp=kcf.params(**cp))
+    ora = F.full_path(rho, u, F.BOX, 4, h, params=cp)
+    check_fields(gpu[0], oracle_as_gpu_layout(ora))
+
+
+def test_constant_and_uniform_velocity(ctx):
+    say("[gpu] constant field / uniform velocity")
+    shape = (12, 13, 14)
+    rho = np.full(shape, 1.25, dtype=np.float32)
+    u = np.stack([np.full(shape, c, dtype=np.float32) for c in (0.3, -0.2, 0.1)])
+    gpu, st = run_gpu(ctx, rho, u, 0.1, [(F.GAUSS, 2)])
+    g = gpu[0]
+    assert np.max(np.abs(g["rho_bar"] - 1.25)) <= 2e-7
+    for i, c in enumerate((0.3, -0.2, 0.1)):
+        assert np.max(np.abs(g["ut"][i] - c)) <= 2e-7
+    assert np.max(np.abs(g["tau"])) <= 1e-7 and np.max(np.abs(g["grad"])) <= 1e-5
+    rho2, _ = synth.random_fields(shape, seed=9, rho_amp=0.3)
+    gpu2, _ = run_gpu(ctx, rho2, u, 0.1, [(F.BOX, 4)])
+    assert np.max(np.abs(gpu2[0]["tau"])) <= 1e-7
+
+
+def test_galilean_invariance(ctx):
+    say("[gpu] galilean invariance of tau and grad")
+    rho, u = synth.random_fields((16, 16, 16), seed=4)
+    U = np.array([0.5, -0.25, 0.125], dtype=np.float32)
+    g1, _ = run_gpu(ctx, rho, u, 0.1, [(F.BOX, 4)])
+    g2, _ = run_gpu(ctx, rho, u + U[:, None, None, None], 0.1, [(F.BOX, 4)])
+    for c in range(6):
+        assert rel(g2[0]["tau"][c], g1[0]["tau"][c]) <= 2e-5
+    for c in range(9):
+        assert rel(g2[0]["grad"][c], g1[0]["grad"][c]) <= 2e-5
+
+
+def test_determinism_and_reduction_exactness(ctx):
+    say("[gpu] determinism and FP64 reductions vs host sums")
+    rho, u = synth.workload_fields("c256_gauss8", n=48)
+    rho, u = rho.numpy(), u.numpy()
+    h = 2 * math.pi / 48
+    g1, s1 = run_gpu(ctx, rho, u, h, [(F.BOX, 4)])
+    g2, s2 = run_gpu(ctx, rho, u, h, [(F.BOX, 4)])
+    assert s1[0]["raw"] == s2[0]["raw"]
+    for f in ALL:
+        assert np.array_equal(g1[0][f], g2[0][f], equal_nan=True)
+    # host FP64 sums of the GPU's own float32 fields
+    g = {k: v.astype(np.float64) for k, v in g1[0].items()}
+    G = g["grad"].reshape(3, 3, *rho.shape)
+    S = 0.5 * (G + G.transpose(1, 0, 2, 3, 4))
+    tau = np.empty((3, 3) + rho.shape)
+    tgm = np.empty((3, 3) + rho.shape)
+    for c, (i, j) in enumerate(PAIRS):
+        tau[i, j] = tau[j, i] = g["tau"][c]
+        tgm[i, j] = tgm[j, i] = g["tau_gm"][c]
+    pi = -np.einsum("ij...,ij...->...", tau, S)
+    pigm = -np.einsum("ij...,ij...->...", tgm, S)
+    raw = s1[0]["raw"]
+    n = rho.size
+    assert raw[0] == n
+    checks = [(1, g["rho_bar"].sum()), (3, pi.sum()), (4, pigm.sum()), (5, (pi * pi).sum()),
+              (7, (pi * pigm).sum())]
+    for c in range(6):
+        checks += [(8 + c, g["tau"][c].sum()), (14 + c, g["tau_gm"][c].sum()),
+                   (20 + c, (g["tau"][c] ** 2).sum()), (32 + c, (g["tau"][c] * g["tau_gm"][c]).sum())]
+    for slot, host in checks:
+        assert abs(raw[slot] - host) <= 1e-10 * abs(host) + 1e-300, (slot, raw[slot], host)
+    # generic reduction entry point
+    a = dev(g1[0]["tau"][0])
+    b = dev(g1[0]["tau_gm"][0])
+    s = ctx.reduce_check(a, b)
+    ha = g1[0]["tau"][0].astype(np.float64)
+    hb = g1[0]["tau_gm"][0].astype(np.float64)
+    assert abs(s[0] - ha.sum()) <= 1e-10 * np.abs(ha).sum()
+    assert abs(s[1] - (ha * ha).sum()) <= 1e-10 * (ha * ha).sum()
+    assert abs(s[2] - (ha * hb).sum()) <= 1e-10 * np.abs(ha * hb).sum()
+
+
+def test_input_stats(ctx):
+    say("[gpu] input statistics (E_k, enstrophy)")
+    n, u0 = 32, 0.1
+    rho, u = synth.taylor_green(n, u0)
+    st = ctx.input_stats(dev(rho), dev(u), 2 * math.pi / n)
+    o = F.input_stats(rho, u, 2 * math.pi / n)
+    assert abs(st["ek"] - o["ek"]) <= 1e-10 * o["ek"]
+    assert abs(st["enstrophy"] - o["enstrophy"]) <= 1e-10 * o["enstrophy"]
+    assert abs(st["ek"] - u0 ** 2 / 8) <= 1e-7 * u0 ** 2
+    rho, u = synth.random_fields((16, 20, 24), seed=5)
+    st = ctx.input_stats(dev(rho), dev(u), 0.1)
+    o = F.input_stats(rho, u, 0.1)
+    for k in ("mean_rho", "ek", "enstrophy"):
+        assert abs(st[k] - o[k]) <= 1e-10 * abs(o[k])
+
+
+def test_grad_closure_standalone(ctx):
+    say("[gpu] standalone gradient/closure pass")
+    rho, u = synth.random_fields((18, 20, 22), seed=6)
+    h = 0.15
+    ora = F.full_path(rho, u, F.BOX, 4, h)
+    rb = dev(ora["rho_bar"])
+    ut = dev(ora["ut"])
+    tau = dev(np.stack([ora["tau"][i, j] for (i, j) in PAIRS]))
+    outs = kcf.alloc_outputs(rho.shape, "cuda", ("grad", "tau_gm", "tau_smag", "k_sgs", "nu_t", "omega_t"))
+    st = ctx.grad_closure(rb, ut, tau, h, ora["delta"], ora["m2"], outs)
+    torch.cuda.synchronize()
+    og = oracle_as_gpu_layout(ora)
+    fields = ("grad", "tau_gm", "tau_smag", "k_sgs", "nu_t", "omega_t")
+    check_fields({k: v.cpu().numpy() for k, v in outs.items()}, og, fields=fields)
+    check_stats(st, ora)
+
+
+def test_error_paths(ctx):
+    say("[gpu] error paths")
+    r = torch.ones((8, 8, 8), device="cuda")
+    u = torch.zeros((3, 8, 8, 8), device="cuda")
+    o = [kcf.alloc_outputs((8, 8, 8), "cuda")]
+    with pytest.raises(kcf.KcfError) as e:
+        ctx.filter_favre(r, u, 0.1, [(F.BOX, 3)], o)
+    assert e.value.code == kcf.EINVAL
+    with pytest.raises(kcf.KcfError) as e:
+        ctx.filter_favre(r, u, 0.1, [(F.BOX, 16)], o)  # 2R+1 = 17 > 8
+    assert e.value.code == kcf.EUNSUPPORTED
+    with pytest.raises(kcf.KcfError) as e:
+        ctx.filter_favre(r, u, 0.1, [(F.GAUSS, 10)], o)  # R = 15 > 12
+    assert e.value.code == kcf.EUNSUPPORTED
+    with pytest.raises(kcf.KcfError) as e:
+        ctx.filter_favre(r, u, 0.1, [], [])
+    assert e.value.code == kcf.EINVAL
+    with pytest.raises(kcf.KcfError) as e:
+        ctx.filter_favre(r, u, -0.1, [(F.BOX, 2)], o)
+    assert e.value.code == kcf.EINVAL
+    with pytest.raises(kcf.KcfError) as e:
+        ctx.filter_favre(r, u, 0.1, [(F.BOX, 2)], o, cp=kcf.params(theta=0.0))
+    assert e.value.code == kcf.EINVAL
+    # NaN input is not an error: it is counted
+    rn = torch.ones((12, 12, 12), device="cuda")
+    rn[3, 4, 5] = float("nan")
+    un = torch.zeros((3, 12, 12, 12), device="cuda")
+    st = ctx.filter_favre(rn, un, 0.1, [(F.BOX, 2)], [kcf.alloc_outputs((12, 12, 12), "cuda")])
+    assert st[0]["n_nonfinite"] > 0 and st[0]["n_points"] + st[0]["n_nonfinite"] == 12 ** 3
+
+
+# ------------------------------------------------------------------ full sizes, sampled points
+def sample_points(shape, k, seed):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    pts = [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (0, ny - 1, 0), (nz - 1, 0, nx - 1),
+           (nz // 2, 11, 15), (nz // 2, 12, 16)]  # tile borders
+    pts += [tuple(int(v) for v in p) for p in
+            np.stack([rng.integers(0, nz, k), rng.integers(0, ny, k), rng.integers(0, nx, k)], 1)]
+    return np.array(pts)
+
+
+def gather(t, pts):
+    idx = torch.as_tensor(pts, device=t.device, dtype=torch.long)
+    return t[:, idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy().astype(np.float64)
+
+
+def check_sampled(ctx, name, n, filters, k, seed):
+    h = 2 * math.pi / n
+    rho_d, u_d = synth.workload_fields(name, device="cuda")
+    rho_h, u_h = rho_d.cpu().numpy(), u_d.cpu().numpy()
+    outs = [kcf.alloc_outputs((n, n, n), "cuda", ("rho_bar", "ut", "tau", "grad", "tau_gm")) for _ in filters]
+    st = ctx.filter_favre(rho_d, u_d, h, filters, outs)
+    torch.cuda.synchronize()
+    pts = sample_points((n, n, n), k, seed)
+    for fi, (kind, nd) in enumerate(filters):
+        say(f"[gpu]   width {nd}h: {len(pts)} sampled points")
+        sp = F.sampled_points(rho_h, u_h, kind, nd, h, pts)
+        got = {f: gather(outs[fi][f], pts) for f in outs[fi]}
+        # maxima of the oracle over the sample set the scale of each component
+        ref = dict(rho_bar=sp["rho_bar"][None], ut=sp["ut"].T,
+                   tau=np.stack([sp["tau"][:, i, j] for (i, j) in PAIRS]),
+                   grad=sp["G"].reshape(-1, 9).T,
+                   tau_gm=np.stack([sp["tau_gm"][:, i, j] for (i, j) in PAIRS]))
+        for f in ref:
+            for c in range(ref[f].shape[0]):
+                e = rel(got[f][c], ref[f][c])
+                assert e <= TOL, (nd, f, c, e)
+        assert st[fi]["n_nonfinite"] == 0 and st[fi]["n_points"] == n ** 3
+    return outs, st
+
+
+def test_c256_gauss8_sampled(ctx):
+    say("[gpu] 256^3 gaussian delta=8h: sampled-point parity")
+    check_sampled(ctx, "c256_gauss8", 256, [(F.GAUSS, 8)], 24, 1)
+
+
+def test_c512_box_multi_sampled(ctx):
+    say("[gpu] 512^3 box 2,4,8,16h fused: sampled-point parity")
+    check_sampled(ctx, "c512_box_multi", 512, [(F.BOX, 2), (F.BOX, 4), (F.BOX, 8), (F.BOX, 16)], 12, 2)
