@@ -166,6 +166,67 @@ int kcf_input_stats(kcf_ctx *ctx, const kcf_grid *grid, const float *rho, const 
  * out[0] = sum a, out[1] = sum a^2, out[2] = sum a*b (b may be NULL: then out[2] = 0). */
 int kcf_reduce_check(kcf_ctx *ctx, const float *a, const float *b, int64_t n, double *out);
 
+/* ---- learned closure ------------------------------------------------------------------
+ * A small MLP, 14 inputs -> 64 -> 64 -> 64 -> 6 outputs, GELU (tanh form) after the hidden
+ * layers, maps the filtered velocity gradient to tau. The paper has no learned closure; this
+ * is the interface of the learned part of the library:
+ *   inputs  (14): g = Delta * G (G_ij = d_j ut_i, central differences, row-major) and the five
+ *                 invariants tr(s^2), tr(r^2), tr(s^3), tr(s r^2), tr(s^2 r^2) of g, s and r being
+ *                 its symmetric and antisymmetric parts;
+ *   targets (6) : tau_c / rho_bar, c = xx xy xz yy yz zz;
+ *   both standardised with training-set means and standard deviations.
+ * Matrix products run on BF16 MFMA with FP32 accumulation (inputs, weights, activations and
+ * back-propagated deltas are rounded to BF16 at the products); biases, GELU, loss and Adam
+ * stay in FP32. Parameters: a float32 vector of 9670 values packed W1 (64x14), b1, W2 (64x64),
+ * b2, W3 (64x64), b3, W4 (6x64), b4, each W row-major (out, in).
+ * Normalisation block (68 floats): x_mean[14], x_std[14], y_mean[6], y_std[6], x_lo[14],
+ * x_hi[14]; x_lo/x_hi bound the standardised inputs seen in training (the envelope). */
+/* The context must outlive every network created on it. */
+int kcf_mlp_create(kcf_ctx *ctx, kcf_mlp **out);  /* zero parameters, identity normalisation */
+void kcf_mlp_destroy(kcf_mlp *mlp);
+int kcf_mlp_set_params(kcf_mlp *mlp, const float *params_host);  /* also resets Adam state */
+int kcf_mlp_get_params(kcf_mlp *mlp, float *params_host);
+int kcf_mlp_set_norm(kcf_mlp *mlp, const float *norm_host);      /* 68 floats, see above */
+int kcf_mlp_get_norm(kcf_mlp *mlp, float *norm_host);
+int kcf_mlp_step_count(kcf_mlp *mlp, int64_t *step);
+
+/* Network inputs x_out (N rows of 14, device) and, when tau and y_out are given, targets
+ * y_out (N rows of 6) of every grid point, from filtered fields of width delta. */
+int kcf_mlp_features(kcf_ctx *ctx, const kcf_grid *grid, const float *rho_bar, const float *ut,
+                     const float *tau, double delta, float *x_out, float *y_out);
+/* FP64 column sums, sums of squares, minima and maxima of an n x ncol row-major device matrix
+ * (host outputs; synchronises). ncol <= 32. */
+int kcf_mlp_column_stats(kcf_ctx *ctx, const float *X, int64_t n, int ncol, double *sum,
+                         double *sumsq, double *mn, double *mx);
+/* Sets the normalisation from a training set (population standard deviations; envelope =
+ * standardised per-column minima and maxima). */
+int kcf_mlp_fit_norm(kcf_mlp *mlp, const float *x, const float *y, int64_t n);
+
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the minibatch
+ * rows idx[0..batch) of the dataset (x: n x 14, y: n x 6, raw, device; idx: device int32,
+ * NULL = rows 0..batch-1). Indices must lie in [0, n); the kernel clamps them to that range.
+ * batch: multiple of 32. loss_dev (device float, may be NULL) receives the batch MSE before
+ * the update. Asynchronous. */
+int kcf_mlp_train_step(kcf_mlp *mlp, const float *x, const float *y, int64_t n,
+                       const int32_t *idx, int batch, float lr, float *loss_dev);
+/* Loss and gradient of the current parameters on a minibatch (host outputs; synchronises). */
+int kcf_mlp_grads(kcf_mlp *mlp, const float *x, const float *y, int64_t n, const int32_t *idx,
+                  int batch, float *grads_host, double *loss_host);
+/* Standardised network outputs (n rows of 6, device) for raw input rows x (n x 14). */
+int kcf_mlp_predict(kcf_mlp *mlp, const float *x, int64_t n, float *y_std);
+/* Learned tau (6N, symmetric-tensor blocks) over a field from rho_bar (N) and ut (3N) of
+ * filter width delta. Points whose standardised inputs leave the envelope, or are not finite,
+ * take the gradient model rho_bar * m2 * G G^T instead. mask (device, ceil(N/16) uint16
+ * words, bit p of word t = point 16 t + p, may be NULL) marks those points; n_fallback (host,
+ * may be NULL; then the call synchronises) counts them. */
+int kcf_mlp_infer_field(kcf_mlp *mlp, const kcf_grid *grid, const float *rho_bar,
+                        const float *ut, double delta, double m2, float *tau, uint16_t *mask,
+                        int64_t *n_fallback);
+/* Checkpoint of parameters, Adam moments, step count and normalisation, with a checksum.
+ * Errors: KCF_EIO for unreadable, truncated or corrupted files. */
+int kcf_mlp_save(kcf_mlp *mlp, const char *path);
+int kcf_mlp_load(kcf_mlp *mlp, const char *path);
+
 #ifdef __cplusplus
 }
 #endif

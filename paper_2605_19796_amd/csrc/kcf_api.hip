@@ -214,6 +214,12 @@ int choose_zchunks(int64_t items_per_chunk, int nz, int R) {
 
 }  // namespace
 
+namespace kcf {
+int api_fail(int code, const char* msg) { return fail(code, msg); }
+hipStream_t ctx_stream(kcf_ctx* c) { return c->stream; }
+int ctx_device(kcf_ctx* c) { return c->device; }
+}  // namespace kcf
+
 extern "C" {
 
 int kcf_version(void) { return 100; }

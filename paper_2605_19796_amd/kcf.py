@@ -83,6 +83,29 @@ _SIGS = {
                                   C.POINTER(InputSummary)]),
     "kcf_reduce_check": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                    C.POINTER(C.c_double)]),
+    "kcf_mlp_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
+    "kcf_mlp_destroy": (None, [C.c_void_p]),
+    "kcf_mlp_set_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    "kcf_mlp_get_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    "kcf_mlp_set_norm": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    "kcf_mlp_get_norm": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
+    "kcf_mlp_step_count": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "kcf_mlp_features": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_double, C.c_void_p, C.c_void_p]),
+    "kcf_mlp_column_stats": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "kcf_mlp_fit_norm": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "kcf_mlp_train_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_int, C.c_float, C.c_void_p]),
+    "kcf_mlp_grads": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
+                                C.POINTER(C.c_float), C.POINTER(C.c_double)]),
+    "kcf_mlp_predict": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
+    "kcf_mlp_infer_field": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p,
+                                      C.c_double, C.c_double, C.c_void_p, C.c_void_p,
+                                      C.POINTER(C.c_int64)]),
+    "kcf_mlp_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "kcf_mlp_load": (C.c_int, [C.c_void_p, C.c_char_p]),
 }
 
 _lib = None
@@ -122,16 +145,16 @@ def filter_taps(kind, delta_over_h, h):
     return [buf[i] for i in range(2 * R.value + 1)], R.value, m2.value
 
 
-def _ptr(t):
+def _ptr(t, dtype=None):
     if t is None:
         return None
+    import torch
     if not t.is_cuda:
         raise ValueError("expected a device tensor")
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
-    import torch
-    if t.dtype != torch.float32:
-        raise ValueError("expected float32")
+    if t.dtype != (dtype or torch.float32):
+        raise ValueError(f"expected {dtype or torch.float32}, got {t.dtype}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -171,9 +194,16 @@ class Context:
         h = C.c_void_p()
         check(self._lib.kcf_ctx_create(C.byref(h), device, C.c_void_p(stream.cuda_stream)))
         self.handle = h
+        self._children = []  # weak references to MLPs that use this context
 
     def close(self):
+        """Destroys the context after every MLP created on it (they must not outlive it)."""
         if self.handle:
+            for ref in self._children:
+                m = ref()
+                if m is not None:
+                    m.close()
+            self._children = []
             self._lib.kcf_ctx_destroy(self.handle)
             self.handle = None
 
@@ -226,3 +256,125 @@ class Context:
         out = (C.c_double * 3)()
         check(self._lib.kcf_reduce_check(self.handle, _ptr(a), _ptr(b), a.numel(), out))
         return list(out)
+
+
+N_PARAMS = 9670
+N_NORM = 68
+
+
+def _f32(a, n):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32).ravel()
+    if a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class MLP:
+    """Learned-closure network state on the GPU (see include/kcf.h)."""
+
+    def __init__(self, ctx: Context):
+        import weakref
+        self.ctx = ctx
+        self._lib = ctx._lib
+        h = C.c_void_p()
+        check(self._lib.kcf_mlp_create(ctx.handle, C.byref(h)))
+        self.handle = h
+        ctx._children.append(weakref.ref(self))
+
+    def close(self):
+        if self.handle:
+            self._lib.kcf_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        a, ptr = _f32(params, N_PARAMS)
+        check(self._lib.kcf_mlp_set_params(self.handle, ptr))
+
+    def get_params(self):
+        import numpy as np
+        a = np.empty(N_PARAMS, dtype=np.float32)
+        check(self._lib.kcf_mlp_get_params(self.handle, a.ctypes.data_as(C.POINTER(C.c_float))))
+        return a
+
+    def set_norm(self, norm):
+        a, ptr = _f32(norm, N_NORM)
+        check(self._lib.kcf_mlp_set_norm(self.handle, ptr))
+
+    def get_norm(self):
+        import numpy as np
+        a = np.empty(N_NORM, dtype=np.float32)
+        check(self._lib.kcf_mlp_get_norm(self.handle, a.ctypes.data_as(C.POINTER(C.c_float))))
+        return a
+
+    def step_count(self):
+        s = C.c_int64()
+        check(self._lib.kcf_mlp_step_count(self.handle, C.byref(s)))
+        return s.value
+
+    def fit_norm(self, x, y):
+        check(self._lib.kcf_mlp_fit_norm(self.handle, _ptr(x), _ptr(y), x.shape[0]))
+
+    def train_step(self, x, y, idx, batch, lr, loss_out=None):
+        import torch
+        check(self._lib.kcf_mlp_train_step(self.handle, _ptr(x), _ptr(y), x.shape[0],
+                                           _ptr(idx, torch.int32), batch, lr, _ptr(loss_out)))
+
+    def grads(self, x, y, idx, batch):
+        import numpy as np
+        import torch
+        g = np.empty(N_PARAMS, dtype=np.float32)
+        loss = C.c_double()
+        check(self._lib.kcf_mlp_grads(self.handle, _ptr(x), _ptr(y), x.shape[0], _ptr(idx, torch.int32),
+                                      batch, g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)))
+        return loss.value, g
+
+    def predict(self, x):
+        import torch
+        y = torch.empty((x.shape[0], 6), dtype=torch.float32, device=x.device)
+        check(self._lib.kcf_mlp_predict(self.handle, _ptr(x), x.shape[0], _ptr(y)))
+        return y
+
+    def infer_field(self, rho_bar, ut, h, delta, m2, tau_out=None, mask_out=None, count=True):
+        import torch
+        nz, ny, nx = rho_bar.shape[-3:]
+        g = Grid(nx, ny, nz, h)
+        if tau_out is None:
+            tau_out = torch.empty((6, nz, ny, nx), dtype=torch.float32, device=rho_bar.device)
+        nfb = C.c_int64()
+        check(self._lib.kcf_mlp_infer_field(self.handle, C.byref(g), _ptr(rho_bar), _ptr(ut), delta, m2,
+                                            _ptr(tau_out), _ptr(mask_out, torch.int16),
+                                            C.byref(nfb) if count else None))
+        return tau_out, (nfb.value if count else None)
+
+    def save(self, path):
+        check(self._lib.kcf_mlp_save(self.handle, os.fsencode(path)))
+
+    def load(self, path):
+        check(self._lib.kcf_mlp_load(self.handle, os.fsencode(path)))
+
+
+def mlp_features(ctx, rho_bar, ut, tau, h, delta, with_targets=True):
+    """Network inputs (N, 14) and targets (N, 6) of every grid point (device tensors)."""
+    import torch
+    nz, ny, nx = rho_bar.shape[-3:]
+    n = nx * ny * nz
+    g = Grid(nx, ny, nz, h)
+    x = torch.empty((n, 14), dtype=torch.float32, device=rho_bar.device)
+    y = torch.empty((n, 6), dtype=torch.float32, device=rho_bar.device) if with_targets else None
+    check(ctx._lib.kcf_mlp_features(ctx.handle, C.byref(g), _ptr(rho_bar), _ptr(ut),
+                                    _ptr(tau) if with_targets else None, delta, _ptr(x), _ptr(y)))
+    return x, y
+
+
+def column_stats(ctx, X):
+    ncol = X.shape[1]
+    arrs = [(C.c_double * ncol)() for _ in range(4)]
+    check(ctx._lib.kcf_mlp_column_stats(ctx.handle, _ptr(X), X.shape[0], ncol, *arrs))
+    return [list(a) for a in arrs]
