@@ -49,8 +49,8 @@ def load_traffic():
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(rho, u, n_sub=96):
-    """The FP64 oracle on a 96^3 periodic sub-cube of the same field, four widths."""
+def cpu_baseline(rho, u, n_sub=192):
+    """The FP64 oracle on a 192^3 periodic sub-cube of the same field, four widths."""
     import numpy as np
     from oracle import fields as F
     r = rho[:n_sub, :n_sub, :n_sub].cpu().numpy()
@@ -65,6 +65,100 @@ def cpu_baseline(rho, u, n_sub=96):
                        f"sub-cube of the 512^3 field ({dt:.1f} s, single thread)")
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _timed(fn, reps, warm=1):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def learned_section(ctx, args):
+    """Training on 256^3 Gaussian-filtered fields (widths 4h, 8h; batch 65536), then the
+    learned closure against the exact explicit-filter path on a 1024^3 field (Gaussian 8h)."""
+    import torch
+    from paper_2605_19796_amd import kcf, learned, synth
+    dev = torch.device("cuda", 0)
+    out = {}
+    n_tr = 256
+    h_tr = 2 * math.pi / n_tr
+    progress("learned: building the 256^3 training set")
+    rho, u = synth.workload_fields("c256_gauss8", device=dev)
+    X, Y = learned.build_dataset(ctx, [(rho, u)], h_tr, widths=(4, 8))
+    del rho, u
+    mlp = kcf.MLP(ctx)
+    mlp.set_params(learned.init_params(7))
+    mlp.fit_norm(X, Y)
+    batch = 65536
+    progress(f"learned: training {args.train_steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = learned.train(mlp, X, Y, steps=args.train_steps, batch=batch, lr=2e-3, lr_final=5e-5,
+                         seed=7, loss_every=max(args.train_steps // 6, 1))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    out["training"] = {
+        "workload": "256^3 Gaussian-filtered fields at 4h and 8h, 33.5M samples, batch 65536, Adam",
+        "samples": int(X.shape[0]), "steps": args.train_steps,
+        "ms_per_step": t_train * 1e3 / args.train_steps,
+        "samples_per_s": args.train_steps * batch / t_train,
+        "loss_history": hist,
+    }
+    del X, Y
+    rho_v, u_v = synth.workload_fields("c256_heldout", device=dev)
+    ev = learned.evaluate(ctx, mlp, rho_v, u_v, h_tr, 8)
+    out["heldout_256"] = {k: ev[k] for k in ("r_learned_mean", "r_gm_mean", "nrmse_learned_mean",
+                                              "nrmse_gm_mean", "fallback", "n", "r_learned")}
+    del rho_v, u_v
+    torch.cuda.empty_cache()
+
+    n = args.learned_n
+    h = 2 * math.pi / n
+    progress(f"learned: {n}^3 learned-vs-plain race")
+    rho, u = synth.workload_fields("c1024_learned", device=dev, n=n)
+    ex = kcf.alloc_outputs((n, n, n), dev, ("rho_bar", "ut", "tau"))
+    st = ctx.filter_favre(rho, u, h, [(kcf.GAUSS, 8)], [ex])
+    m2 = st[0]["m2"]
+    tau_l = torch.empty((6, n, n, n), dtype=torch.float32, device=dev)
+    tau_gm = torch.empty((6, n, n, n), dtype=torch.float32, device=dev)
+    reps = 3
+    # plain closure path: exact tau by explicit filtering of rho, u (statistics off)
+    t_plain = _timed(lambda: ctx.filter_favre(rho, u, h, [(kcf.GAUSS, 8)], [ex], stats=False), reps)
+    # learned path: tau from rho_bar, ut (features, BF16 MFMA MLP, envelope fallback)
+    t_learned = _timed(lambda: mlp.infer_field(ex["rho_bar"], ex["ut"], h, 8 * h, m2, tau_out=tau_l,
+                                               count=False), reps)
+    # gradient-model path: tau_gm from rho_bar, ut
+    t_gm = _timed(lambda: ctx.grad_closure(ex["rho_bar"], ex["ut"], None, h, 8 * h, m2,
+                                           {"tau_gm": tau_gm}, stats=False), reps)
+    _, nfb = mlp.infer_field(ex["rho_bar"], ex["ut"], h, 8 * h, m2, tau_out=tau_l)
+    r_l = [learned.pearson_gpu(ctx, tau_l[c], ex["tau"][c]) for c in range(6)]
+    r_g = [learned.pearson_gpu(ctx, tau_gm[c], ex["tau"][c]) for c in range(6)]
+    nr_l = [learned.nrmse_gpu(ctx, tau_l[c], ex["tau"][c]) for c in range(6)]
+    nr_g = [learned.nrmse_gpu(ctx, tau_gm[c], ex["tau"][c]) for c in range(6)]
+    pts = float(n) ** 3
+    out["race"] = {
+        "workload": f"{n}^3 spectral turbulence (k0 {32 * n / 1024:g}), Gaussian filter 8h",
+        "plain_exact_ms": t_plain, "learned_ms": t_learned, "gradient_model_ms": t_gm,
+        "learned_points_per_s": pts / (t_learned * 1e-3),
+        "plain_points_per_s": pts / (t_plain * 1e-3),
+        "learned_speedup_vs_plain": t_plain / t_learned,
+        "r_learned": r_l, "r_learned_mean": sum(r_l) / 6, "r_gm_mean": sum(r_g) / 6,
+        "nrmse_learned_mean": sum(nr_l) / 6, "nrmse_gm_mean": sum(nr_g) / 6,
+        "fallback_points": nfb, "points": int(pts),
+        "learned_mfma_tflops": 18944 * pts / (t_learned * 1e-3) / 1e12,
+    }
+    mlp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +166,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-n", type=int, default=1024, help="grid of the learned-vs-plain race")
+    ap.add_argument("--train-steps", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the filtering path here is a single-GPU build "
@@ -95,6 +192,7 @@ def main():
         ist = ctx.input_stats(rho, u, h)
         return st, ist
 
+    progress(f"{n}^3 fused 4-width pass: warmup")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -145,7 +243,13 @@ def main():
         "input": ist,
     }
     if not args.no_cpu_baseline:
+        progress("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(rho, u)
+    del outs
+    if not args.no_learned:
+        del rho, u
+        torch.cuda.empty_cache()
+        line["learned"] = learned_section(ctx, args)
     ctx.close()
     print(json.dumps(line), flush=True)
 

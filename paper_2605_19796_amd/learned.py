@@ -69,7 +69,7 @@ def train(mlp, X, Y, steps, batch=65536, lr=1e-3, lr_final=1e-4, seed=7, loss_ev
         frac = s / max(steps - 1, 1)
         cur = lr * (lr_final / lr) ** frac
         mlp.train_step(X, Y, idx, batch, cur, losses[s:s + 1])
-        if (s + 1) % loss_every == 0 or s == steps - 1:
+        if s == 0 or (s + 1) % loss_every == 0 or s == steps - 1:
             v = float(losses[s].item())
             hist.append((s + 1, v))
             if on_loss:

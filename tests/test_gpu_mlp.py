@@ -244,7 +244,7 @@ def test_inference_matches_oracle_and_fallback(ctx):
 
 def test_training_beats_gradient_model(ctx):
     say("[gpu] training on filtered fields; learned vs gradient model on a held-out field")
-    n = 64
+    n = 128
     h = 2 * math.pi / n
     train_fields = [tuple(t.cuda() for t in synth.workload_fields("c256_gauss8", n=n))]
     X, Y = learned.build_dataset(ctx, train_fields, h, widths=(4, 8))
