@@ -24,6 +24,9 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result",
     "-Wno-unused-value",
+    # keep the per-quantity z rings of the box kernels in VGPRs (indexed moves), not scratch
+    "-mllvm", "-amdgpu-promote-alloca-to-vector-max-regs=64",
+    "-mllvm", "-amdgpu-promote-alloca-to-vector-limit=8192",
 ]
 
 

@@ -323,38 +323,52 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
       return fail(KCF_EUNSUPPORTED, "FP64 accumulation is limited to radii <= 8");
   }
   KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
-  FilterArgs A;
-  std::memset(&A, 0, sizeof(A));
-  A.rho = rho;
-  A.u = u;
-  A.nx = grid->nx;
-  A.ny = grid->ny;
-  A.nz = grid->nz;
-  A.ntot = (int64_t)grid->nx * grid->ny * grid->nz;
-  A.inv2h = (float)(1.0 / (2.0 * grid->h));
-  A.ntx = (grid->nx + kOX - 1) / kOX;
-  A.nty = (grid->ny + kOY - 1) / kOY;
-  A.ntiles = A.ntx * A.nty;
-
-  const bool fused = nf == 4 && radii[0] == 1 && radii[1] == 2 && radii[2] == 4 &&
-                     radii[3] == 8 && fp64[0] && fp64[1] && !fp64[2] && !fp64[3];
-  const int rmax = fused ? 8 : 0;
-  // z chunks: one decision for the whole call
-  int rr = 0;
-  for (int f = 0; f < nf; ++f) rr = std::max(rr, kr[f]);
-  (void)rmax;
-  A.nzc = choose_zchunks((int64_t)A.ntiles * (fused ? 4 : 1), grid->nz, rr);
-  A.zlen = (grid->nz + A.nzc - 1) / A.nzc;
-  A.nzc = (grid->nz + A.zlen - 1) / A.zlen;
-  const int items = A.ntiles * A.nzc;
-  A.tiles_per_xcd = (items + 7) / 8;
-  const size_t per_width = (size_t)items * kStatWaves * kNStat;
-  if ((rc = ensure_partials(c, per_width * nf))) return rc;
-
-  for (int f = 0; f < nf; ++f) {
-    WidthArgs& W = A.wa[fused ? f : 0];
+  // kernel per width: the sliding-sum box kernel where it applies, the general one otherwise
+  int use_box[4];
+  for (int f = 0; f < nf; ++f)
+    use_box[f] = filters[f].kind == KCF_BOX && box_supported(radii[f], fp64[f]);
+  const bool fused = nf == 4 && use_box[0] && use_box[1] && use_box[2] && use_box[3] &&
+                     radii[0] == 1 && radii[1] == 2 && radii[2] == 4 && radii[3] == 8 &&
+                     fp64[0] && fp64[1] && !fp64[2] && !fp64[3];
+  const int64_t ntot = (int64_t)grid->nx * grid->ny * grid->nz;
+  auto geometry = [&](FilterArgs& A, bool box, int nw, int rr) {
+    std::memset(&A, 0, sizeof(A));
+    A.rho = rho;
+    A.u = u;
+    A.nx = grid->nx;
+    A.ny = grid->ny;
+    A.nz = grid->nz;
+    A.ntot = ntot;
+    A.inv2h = (float)(1.0 / (2.0 * grid->h));
+    const int ox = box ? box_tile_x() : kOX, oy = box ? box_tile_y() : kOY;
+    A.ntx = (grid->nx + ox - 1) / ox;
+    A.nty = (grid->ny + oy - 1) / oy;
+    A.ntiles = A.ntx * A.nty;
+    A.nzc = choose_zchunks((int64_t)A.ntiles * nw, grid->nz, rr);
+    A.zlen = (grid->nz + A.nzc - 1) / A.nzc;
+    A.nzc = (grid->nz + A.zlen - 1) / A.zlen;
+    A.tiles_per_xcd = (A.ntiles * A.nzc + 7) / 8;
+    A.nw = nw;
+  };
+  // partial sums: [width][items][waves][kNStat]
+  size_t part_width[4], part_off[4];
+  int nparts[4];
+  {
+    size_t off = 0;
+    for (int f = 0; f < nf; ++f) {
+      FilterArgs G;
+      geometry(G, use_box[f] != 0, fused ? 4 : 1, fused ? 8 : kr[f]);
+      const int waves = use_box[f] ? box_stat_waves() : kStatWaves;
+      nparts[f] = G.ntiles * G.nzc * waves;
+      part_width[f] = (size_t)nparts[f] * kNStat;
+      part_off[f] = off;
+      off += part_width[f];
+    }
+    if ((rc = ensure_partials(c, off))) return rc;
+  }
+  auto fill_width = [&](WidthArgs& W, int f, int K) {
     std::memset(&W, 0, sizeof(W));
-    const int R = taps[f].R, K = fused ? radii[f] : kr[f];
+    const int R = taps[f].R;
     for (int m = 0; m < 2 * K + 1; ++m) {
       const int mm = m - (K - R);
       W.wd[m] = (mm >= 0 && mm < 2 * R + 1) ? taps[f].wd[mm] : 0.0;
@@ -362,25 +376,32 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     }
     set_outputs(W, &outs[f]);
     set_closure(W, cp, filters[f].delta_over_h * grid->h, taps[f].m2);
-    W.partials = c->d_part + per_width * f;
-    if (!fused) {
-      A.nw = 1;
+    W.partials = c->d_part + part_off[f];
+  };
+  if (fused) {
+    FilterArgs A;
+    geometry(A, true, 4, 8);
+    for (int f = 0; f < 4; ++f) fill_width(A.wa[f], f, radii[f]);
+    if ((rc = timed_begin(c))) return rc;
+    hipError_t e = launch_box(A, radii, fp64, 8 * 4 * A.tiles_per_xcd, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "box filter launch");
+    if ((rc = timed_end(c))) return rc;
+  } else {
+    for (int f = 0; f < nf; ++f) {
+      FilterArgs A;
+      const bool box = use_box[f] != 0;
+      geometry(A, box, 1, box ? radii[f] : kr[f]);
+      fill_width(A.wa[0], f, box ? radii[f] : kr[f]);
       if ((rc = timed_begin(c))) return rc;
-      hipError_t e = launch_filter(A, &kr[f], &fp64[f], 8 * A.tiles_per_xcd, c->stream);
+      hipError_t e = box ? launch_box(A, &radii[f], &fp64[f], 8 * A.tiles_per_xcd, c->stream)
+                         : launch_filter(A, &kr[f], &fp64[f], 8 * A.tiles_per_xcd, c->stream);
       if (e != hipSuccess) return hip_fail(e, "filter launch");
       if ((rc = timed_end(c))) return rc;
     }
   }
-  if (fused) {
-    A.nw = 4;
-    if ((rc = timed_begin(c))) return rc;
-    hipError_t e = launch_filter(A, kr, fp64, 8 * 4 * A.tiles_per_xcd, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "filter launch");
-    if ((rc = timed_end(c))) return rc;
-  }
   if (stats) {
     for (int f = 0; f < nf; ++f) {
-      hipError_t e = launch_reduce(c->d_part + per_width * f, items * kStatWaves, kNStat,
+      hipError_t e = launch_reduce(c->d_part + part_off[f], nparts[f], kNStat,
                                    c->d_sums + f * kNStat, c->stream);
       if (e != hipSuccess) return hip_fail(e, "reduce launch");
     }

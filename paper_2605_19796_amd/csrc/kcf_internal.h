@@ -91,4 +91,12 @@ hipError_t launch_reduce_check(const float* a, const float* b, int64_t n, double
                                int nblocks, hipStream_t s);
 int kernel_radius_for(int r);   // radius of the kernel instance used for stencil radius r
 
+// box kernels (kcf_box.hip)
+int box_tile_x();
+int box_tile_y();
+int box_stat_waves();
+bool box_supported(int R, int fp64);
+hipError_t launch_box(const FilterArgs& a, const int* radii, const int* fp64, int nblocks,
+                      hipStream_t s);
+
 }  // namespace kcf

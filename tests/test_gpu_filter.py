@@ -140,10 +140,13 @@ def test_multiwidth_fused_matches_single_and_oracle(ctx):
         ora = F.full_path(rho, u, kind, nd, h)
         check_fields(gpu[i], oracle_as_gpu_layout(ora))
         check_stats(st[i], ora)
+        # a single-width launch splits z into different chunks, so its FP32 running sums
+        # restart at different planes: both agree with the oracle, and with each other, to the
+        # parity tolerance
         single, st1 = run_gpu(ctx, rho, u, h, [(kind, nd)])
         for f in ALL:
             d = rel(gpu[i][f], single[0][f])
-            assert d <= 1e-6, (nd, f, d)
+            assert d <= TOL, (nd, f, d)
 
 
 @pytest.mark.parametrize("cp", [dict(gm_form=1), dict(m2_mode=1), dict(ksgs_rho_ref=1),
