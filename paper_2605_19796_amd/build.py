@@ -20,13 +20,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++20", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result",
     "-Wno-unused-value",
-    # keep the per-quantity z rings of the box kernels in VGPRs (indexed moves), not scratch
-    "-mllvm", "-amdgpu-promote-alloca-to-vector-max-regs=64",
-    "-mllvm", "-amdgpu-promote-alloca-to-vector-limit=8192",
 ]
 
 

@@ -192,9 +192,9 @@ int timed_end(kcf_ctx* c) {
 }
 
 // Number of z chunks: enough workgroups to fill the chip, balanced against the 2R+2 planes
-// each chunk spends filling its ring.
-int choose_zchunks(int64_t items_per_chunk, int nz, int R) {
-  const double cus = 256.0;
+// each chunk spends filling its window.
+int choose_zchunks(int64_t items_per_chunk, int nz, int R, int blocks_per_cu) {
+  const double cus = 256.0 * blocks_per_cu;
   double best = -1;
   int best_n = 1;
   for (int n = 1; n <= 16; ++n) {
@@ -327,11 +327,11 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
   int use_box[4];
   for (int f = 0; f < nf; ++f)
     use_box[f] = filters[f].kind == KCF_BOX && box_supported(radii[f], fp64[f]);
-  const bool fused = nf == 4 && use_box[0] && use_box[1] && use_box[2] && use_box[3] &&
-                     radii[0] == 1 && radii[1] == 2 && radii[2] == 4 && radii[3] == 8 &&
-                     fp64[0] && fp64[1] && !fp64[2] && !fp64[3];
   const int64_t ntot = (int64_t)grid->nx * grid->ny * grid->nz;
-  auto geometry = [&](FilterArgs& A, bool box, int nw, int rr) {
+  auto geometry = [&](FilterArgs& A, int f) {
+    const bool box = use_box[f] != 0;
+    const BoxGeom bg = box ? box_geometry(radii[f], fp64[f]) : BoxGeom{};
+    const int rr = box ? radii[f] : kr[f];
     std::memset(&A, 0, sizeof(A));
     A.rho = rho;
     A.u = u;
@@ -340,15 +340,15 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     A.nz = grid->nz;
     A.ntot = ntot;
     A.inv2h = (float)(1.0 / (2.0 * grid->h));
-    const int ox = box ? box_tile_x() : kOX, oy = box ? box_tile_y() : kOY;
+    const int ox = box ? bg.tile_x : kOX, oy = box ? bg.tile_y : kOY;
     A.ntx = (grid->nx + ox - 1) / ox;
     A.nty = (grid->ny + oy - 1) / oy;
     A.ntiles = A.ntx * A.nty;
-    A.nzc = choose_zchunks((int64_t)A.ntiles * nw, grid->nz, rr);
+    A.nzc = choose_zchunks(A.ntiles, grid->nz, rr, box ? bg.blocks_per_cu : 1);
     A.zlen = (grid->nz + A.nzc - 1) / A.nzc;
     A.nzc = (grid->nz + A.zlen - 1) / A.zlen;
     A.tiles_per_xcd = (A.ntiles * A.nzc + 7) / 8;
-    A.nw = nw;
+    A.nw = 1;
   };
   // partial sums: [width][items][waves][kNStat]
   size_t part_width[4], part_off[4];
@@ -357,8 +357,8 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     size_t off = 0;
     for (int f = 0; f < nf; ++f) {
       FilterArgs G;
-      geometry(G, use_box[f] != 0, fused ? 4 : 1, fused ? 8 : kr[f]);
-      const int waves = use_box[f] ? box_stat_waves() : kStatWaves;
+      geometry(G, f);
+      const int waves = use_box[f] ? box_geometry(radii[f], fp64[f]).stat_waves : kStatWaves;
       nparts[f] = G.ntiles * G.nzc * waves;
       part_width[f] = (size_t)nparts[f] * kNStat;
       part_off[f] = off;
@@ -378,26 +378,16 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     set_closure(W, cp, filters[f].delta_over_h * grid->h, taps[f].m2);
     W.partials = c->d_part + part_off[f];
   };
-  if (fused) {
+  for (int f = 0; f < nf; ++f) {
     FilterArgs A;
-    geometry(A, true, 4, 8);
-    for (int f = 0; f < 4; ++f) fill_width(A.wa[f], f, radii[f]);
+    const bool box = use_box[f] != 0;
+    geometry(A, f);
+    fill_width(A.wa[0], f, box ? radii[f] : kr[f]);
     if ((rc = timed_begin(c))) return rc;
-    hipError_t e = launch_box(A, radii, fp64, 8 * 4 * A.tiles_per_xcd, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "box filter launch");
+    hipError_t e = box ? launch_box(A, radii[f], fp64[f], 8 * A.tiles_per_xcd, c->stream)
+                       : launch_filter(A, &kr[f], &fp64[f], 8 * A.tiles_per_xcd, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "filter launch");
     if ((rc = timed_end(c))) return rc;
-  } else {
-    for (int f = 0; f < nf; ++f) {
-      FilterArgs A;
-      const bool box = use_box[f] != 0;
-      geometry(A, box, 1, box ? radii[f] : kr[f]);
-      fill_width(A.wa[0], f, box ? radii[f] : kr[f]);
-      if ((rc = timed_begin(c))) return rc;
-      hipError_t e = box ? launch_box(A, &radii[f], &fp64[f], 8 * A.tiles_per_xcd, c->stream)
-                         : launch_filter(A, &kr[f], &fp64[f], 8 * A.tiles_per_xcd, c->stream);
-      if (e != hipSuccess) return hip_fail(e, "filter launch");
-      if ((rc = timed_end(c))) return rc;
-    }
   }
   if (stats) {
     for (int f = 0; f < nf; ++f) {

@@ -1,20 +1,25 @@
 // Box-filter kernels (gfx950): trapezoidal top-hat of width 2R h, all ten filtered quantities
-// of a column in one thread, sliding sums along x, y and z.
+// of a column in one thread, sliding sums along x and y, a running window sum along z.
 //
-// A workgroup of 512 threads owns an 18x28 column tile (16x26 output columns plus the
-// one-cell halo of the central-difference gradient) and marches along z:
-//   * staging: each arriving plane (with an R-cell halo) is read once from HBM (prefetched one
-//     plane ahead) and turned into the ten products rho, rho u_i, rho u_i u_j in LDS;
-//   * x pass and y pass: every task slides a trapezoid window over one row (column) of one
-//     quantity in registers, about four operations per output instead of 2R+1 taps;
-//   * z pass: every column thread keeps the last 2R x-y filtered planes of its ten quantities
-//     in register rings indexed by a uniform slot (indexed moves, no rotation) and updates a
-//     running window sum, re-seeded from the ring every 2R planes;
-//   * epilogue: Favre velocity and tau in registers; the velocity of three planes goes to LDS
-//     for the gradient, which is evaluated one plane behind together with the closures and
-//     the FP64 statistics.
-// T is the accumulation type: double for narrow widths, where tau is a small difference of
-// large filtered products, float otherwise. Outputs are float32.
+// A workgroup of 256 threads owns an 18x14 column tile (16x12 output columns plus the
+// one-cell halo of the central-difference gradient) and marches along z; two workgroups
+// share a CU, so that one computes while the other waits at a barrier. At step k the
+// plane za = za0 + k arrives:
+//   * staging: the inputs of plane za and of plane za - 2R (the one leaving the window; it is
+//     read a second time, from cache) are prefetched one step ahead and turned into the
+//     differences d = P(za) - P(za - 2R) of the ten products P = rho, rho u_i, rho u_i u_j;
+//   * x pass and y pass, in place in one LDS buffer: each task slides a trapezoid window
+//     over one row (column) of one quantity in registers, about four operations per output;
+//   * z: since the x-y filter is linear, the filtered d is the change of the 2R-plane boxcar
+//     sum B of the filtered products; B is kept per column thread in FP64, and the trapezoid
+//     of plane za - R is the mean of two consecutive boxcars, (B_{k-1} + B_k) / (2n);
+//   * epilogue: Favre velocity and tau from the FP64 window sums; the velocity of three
+//     planes goes to LDS for the gradient, which is evaluated one plane behind together
+//     with the closures and the FP64 statistics.
+// T is the type of the products and of the x-y passes: double for narrow widths, where tau
+// is a small difference of large filtered products, float otherwise. Outputs are float32.
+#include <type_traits>
+
 #include "kcf_device.h"
 
 namespace kcf {
@@ -23,24 +28,45 @@ namespace {
 
 using namespace dev;
 
-constexpr int kBX = 18, kBY = 28;            // computed columns of a tile
-constexpr int kBOX = kBX - 2, kBOY = kBY - 2;  // output columns
-constexpr int kBN = kBX * kBY;               // 504 column threads
-constexpr int kBT = 512;                     // threads per workgroup (8 full waves)
-constexpr int kBYP = kBY / 2;                // rows per y-pass task
+constexpr int kBX = 18;       // computed columns of a tile along x (16 outputs + halo)
+constexpr int kBOX = kBX - 2;
+constexpr int kLdsPerCU = 160 * 1024;
 
-template <int R, typename T>
+// Tile and workgroup shape. Narrow windows use short tiles (18x14 columns, 256 threads) so
+// that three workgroups share a CU; wide windows use tall tiles (18x28, 512 threads), where
+// the 2R-cell halo of a short tile would cost more than the lost occupancy.
+template <int BY_, int BT_, int WAVES_>
+struct BoxCfg {
+  static constexpr int BY = BY_;         // computed rows
+  static constexpr int BOY = BY - 2;     // output rows
+  static constexpr int BN = kBX * BY;    // column threads
+  static constexpr int BT = BT_;         // threads per workgroup
+  static constexpr int WAVES = WAVES_;   // waves per SIMD the register budget allows
+  static constexpr int YP = BT >= 512 ? 2 : 1;  // y-pass tasks per (quantity, column)
+  static constexpr int BYP = BY / YP;    // rows per y-pass task
+  static_assert(BN <= BT && BY % YP == 0 && BT % 64 == 0, "tile does not fit the workgroup");
+};
+using ShortTile = BoxCfg<14, 256, 3>;
+using TallTile = BoxCfg<28, 512, 2>;
+template <int R>
+using TileFor = typename std::conditional<(R <= 4), ShortTile, TallTile>::type;
+
+// One buffer of 10 planes of HY rows with an odd row stride (conflict-free row-per-lane
+// access): products, then x-filtered rows (first kBX entries), then y-filtered rows.
+template <int R, typename T, class C = TileFor<R>>
 struct BoxLds {
   static constexpr int HX = kBX + 2 * R;
-  static constexpr int HY = kBY + 2 * R;
+  static constexpr int HY = C::BY + 2 * R;
+  static constexpr int HXP = HX | 1;
   static constexpr int NRAW = HX * HY;
-  static constexpr int prod = 10 * NRAW * (int)sizeof(T);     // products, then y-filtered planes
-  static constexpr int yf = 10 * kBN * (int)sizeof(T);
-  static constexpr int p0 = ((prod > yf ? prod : yf) + 15) / 16 * 16;
-  static constexpr int xf = 10 * HY * kBX * (int)sizeof(T);
-  static constexpr int su = 9 * kBN * 4;                       // ut of three planes
-  static constexpr int bytes = p0 + xf + su;
+  static constexpr int prod = (10 * HY * HXP * (int)sizeof(T) + 15) / 16 * 16;
+  static constexpr int su = 9 * C::BN * 4;  // ut of three planes
+  static constexpr int bytes = prod + su;
   static constexpr int doubles = (bytes + 7) / 8;
+  // resident workgroups per CU: the smaller of the register and the LDS limit
+  static constexpr int by_waves = C::WAVES * 4 / (C::BT / 64);
+  static constexpr int by_lds = kLdsPerCU / bytes;
+  static constexpr int blocks_per_cu = by_waves < by_lds ? by_waves : by_lds;
 };
 
 // Trapezoid window over v[o .. o + 2R]: (1/n)(sum of the interior + half the two ends).
@@ -57,38 +83,38 @@ __device__ __forceinline__ T trap_last(const T* v, int o, T J, T inv_n) {
   return inv_n * (J + (T)0.5 * (v[o] - v[o + 2 * R]));
 }
 
-// One ring of the last 2R planes of one quantity (a plain array, so that the compiler keeps
-// it in VGPRs and indexes it with the uniform slot); J is the sum of the 2R planes
-// z_o - R + 1 .. z_o + R of the current window.
-template <int R, typename T>
-__device__ __forceinline__ T ring_push(T (&r)[2 * R], T& J, T v, int slot, T inv_n) {
-  const T old = r[slot];
-  r[slot] = v;
-  J += v - old;
-  return inv_n * (J + (T)0.5 * (old - v));
-}
-
-template <int R, typename T>
-__device__ __forceinline__ void ring_reseed(const T (&r)[2 * R], T& J) {
-  T s = 0;
-#pragma unroll
-  for (int t = 0; t < 2 * R; ++t) s += r[t];
-  J = s;
+template <typename T>
+__device__ __forceinline__ void products(const float (&f)[4], T (&p)[10]) {
+  const T r = (T)f[0], ux = (T)f[1], uy = (T)f[2], uz = (T)f[3];
+  const T mx = r * ux, my = r * uy, mz = r * uz;
+  p[0] = r;
+  p[1] = mx;
+  p[2] = my;
+  p[3] = mz;
+  p[4] = mx * ux;
+  p[5] = mx * uy;
+  p[6] = mx * uz;
+  p[7] = my * uy;
+  p[8] = my * uz;
+  p[9] = mz * uz;
 }
 
 template <int R, typename T>
 __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W, int item,
                                          unsigned char* smem) {
   using L = BoxLds<R, T>;
+  using C = TileFor<R>;
+  constexpr int kBT = C::BT, kBN = C::BN, kBOY = C::BOY, kYP = C::YP, kBYP = C::BYP;
   constexpr int HX = L::HX;
   constexpr int HY = L::HY;
+  constexpr int HXP = L::HXP;
   constexpr int NRAW = L::NRAW;
   constexpr int NPF = (NRAW + kBT - 1) / kBT;
-  T* prod = reinterpret_cast<T*>(smem);                   // 10 x HY x HX
-  T* yf = prod;                                           // 10 x kBN (after the x pass)
-  T* xf = reinterpret_cast<T*>(smem + L::p0);             // 10 x HY x kBX
-  float* su = reinterpret_cast<float*>(smem + L::p0 + L::xf);  // 3 planes x 3 x kBN
+  constexpr int QS = HY * HXP;  // stride of one quantity in the buffer
+  T* buf = reinterpret_cast<T*>(smem);
+  float* su = reinterpret_cast<float*>(smem + L::prod);  // 3 planes x 3 x kBN
   const T inv_n = (T)1 / (T)(2 * R);
+  const double inv_2n = 1.0 / (4.0 * R);
 
   const int tid = threadIdx.x;
   const int tile = item % A.ntiles;
@@ -102,19 +128,22 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   const int64_t plane = (int64_t)A.nx * A.ny;
   const int64_t ntot = A.ntot;
 
-  int pfoff[NPF];
+  int pfoff[NPF], ldoff[NPF];
 #pragma unroll
   for (int i = 0; i < NPF; ++i) {
     const int p = tid + i * kBT;
     if (p < NRAW) {
       const int hx = p % HX, hy = p / HX;
       pfoff[i] = wrapi(y0 - R + hy, A.ny) * A.nx + wrapi(x0 - R + hx, A.nx);
+      ldoff[i] = hy * HXP + hx;
     } else {
       pfoff[i] = -1;
+      ldoff[i] = 0;
     }
   }
-  float pf[NPF][4];
-  auto load_plane = [&](int za) {
+  // inputs of the arriving plane (pn) and of the plane leaving the window (po)
+  float pn[NPF][4], po[NPF][4];
+  auto load = [&](float (&pf)[NPF][4], int za) {
     const int64_t zoff = (int64_t)wrapi(za, A.nz) * plane;
 #pragma unroll
     for (int i = 0; i < NPF; ++i) {
@@ -127,7 +156,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
       }
     }
   };
-  load_plane(za0);
+  load(pn, za0);
 
   const bool col_thread = tid < kBN;
   const int col = col_thread ? tid : 0;
@@ -135,107 +164,101 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   const int gx = x0 + cx, gy = y0 + cy;
   const bool interior = col_thread && cx >= 1 && cx <= kBOX && cy >= 1 && cy <= kBOY &&
                         gx < A.nx && gy < A.ny;
+  const int ycol = cy * HXP + cx;  // this column's entry in a y-filtered plane
 
-  T r0[2 * R], r1[2 * R], r2[2 * R], r3[2 * R], r4[2 * R], r5[2 * R], r6[2 * R], r7[2 * R],
-      r8[2 * R], r9[2 * R];
+  double B[10];  // boxcar sums of the 2R planes za - 2R + 1 .. za
 #pragma unroll
-  for (int t = 0; t < 2 * R; ++t)
-    r0[t] = r1[t] = r2[t] = r3[t] = r4[t] = r5[t] = r6[t] = r7[t] = r8[t] = r9[t] = 0;
-  T Jz[10];
-#pragma unroll
-  for (int q = 0; q < 10; ++q) Jz[q] = 0;
+  for (int q = 0; q < 10; ++q) B[q] = 0.0;
   float lag_rb = 1.f, lag_tau[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  double acc[5] = {0, 0, 0, 0, 0};
+  StatAcc acc;
+  stat_zero(acc);
 
   for (int k = 0; k < nsteps; ++k) {
     const int za = za0 + k;
-    // ---- stage plane za as the ten products
+    const bool leaving = k >= 2 * R;  // uniform: plane za - 2R is inside the window
+    // ---- staging: product differences of plane za
 #pragma unroll
     for (int i = 0; i < NPF; ++i) {
       if (pfoff[i] >= 0) {
-        const int p = tid + i * kBT;
-        const T r = (T)pf[i][0];
-        const T ux = (T)pf[i][1], uy = (T)pf[i][2], uz = (T)pf[i][3];
-        const T mx = r * ux, my = r * uy, mz = r * uz;
-        prod[p] = r;
-        prod[NRAW + p] = mx;
-        prod[2 * NRAW + p] = my;
-        prod[3 * NRAW + p] = mz;
-        prod[4 * NRAW + p] = mx * ux;
-        prod[5 * NRAW + p] = mx * uy;
-        prod[6 * NRAW + p] = mx * uz;
-        prod[7 * NRAW + p] = my * uy;
-        prod[8 * NRAW + p] = my * uz;
-        prod[9 * NRAW + p] = mz * uz;
+        T d[10];
+        products<T>(pn[i], d);
+        if (leaving) {
+          T o[10];
+          products<T>(po[i], o);
+#pragma unroll
+          for (int q = 0; q < 10; ++q) d[q] -= o[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 10; ++q) buf[q * QS + ldoff[i]] = d[q];
       }
     }
     __syncthreads();
-    if (k + 1 < nsteps) load_plane(za + 1);
-    // ---- x pass: one (quantity, row) per task
+    if (k + 1 < nsteps) {
+      load(pn, za + 1);
+      if (k + 1 >= 2 * R) load(po, za + 1 - 2 * R);
+    }
+    // ---- x pass, in place: one (quantity, row) per task
     for (int t = tid; t < 10 * HY; t += kBT) {
-      const T* v = prod + t * HX;
+      T* v = buf + t * HXP;
       T vr[HX];
 #pragma unroll
       for (int i = 0; i < HX; ++i) vr[i] = v[i];
       T J = 0;
 #pragma unroll
       for (int i = 1; i <= 2 * R; ++i) J += vr[i];
-      T* dst = xf + t * kBX;
 #pragma unroll
-      for (int o = 0; o < kBX - 1; ++o) dst[o] = trap_slide<R, T>(vr, o, J, inv_n);
-      dst[kBX - 1] = trap_last<R, T>(vr, kBX - 1, J, inv_n);
+      for (int o = 0; o < kBX - 1; ++o) v[o] = trap_slide<R, T>(vr, o, J, inv_n);
+      v[kBX - 1] = trap_last<R, T>(vr, kBX - 1, J, inv_n);
     }
     __syncthreads();
-    // ---- y pass: one (quantity, column, half of the rows) per task
-    for (int t = tid; t < 20 * kBX; t += kBT) {
-      const int x = t % kBX;
-      const int part = (t / kBX) & 1;
-      const int q = t / (2 * kBX);
-      const T* src = xf + (q * HY + part * kBYP) * kBX + x;
-      T vr[kBYP + 2 * R];
+    // ---- y pass, in place: one (quantity, column, half of the rows) per task; all reads
+    // are done before the barrier, all writes after it
+    {
+      constexpr int NYT = 10 * kYP * kBX;
+      constexpr int NYI = (NYT + kBT - 1) / kBT;
+      T vr[NYI][kBYP + 2 * R];
 #pragma unroll
-      for (int i = 0; i < kBYP + 2 * R; ++i) vr[i] = src[i * kBX];
-      T J = 0;
+      for (int j = 0; j < NYI; ++j) {
+        const int t = tid + j * kBT;
+        if (t < NYT) {
+          const int x = t % kBX, part = (t / kBX) % kYP, q = t / (kYP * kBX);
+          const T* src = buf + q * QS + part * kBYP * HXP + x;
 #pragma unroll
-      for (int i = 1; i <= 2 * R; ++i) J += vr[i];
-      T* dst = yf + q * kBN + part * kBYP * kBX + x;
+          for (int i = 0; i < kBYP + 2 * R; ++i) vr[j][i] = src[i * HXP];
+        }
+      }
+      __syncthreads();
 #pragma unroll
-      for (int o = 0; o < kBYP - 1; ++o) dst[o * kBX] = trap_slide<R, T>(vr, o, J, inv_n);
-      dst[(kBYP - 1) * kBX] = trap_last<R, T>(vr, kBYP - 1, J, inv_n);
+      for (int j = 0; j < NYI; ++j) {
+        const int t = tid + j * kBT;
+        if (t < NYT) {
+          const int x = t % kBX, part = (t / kBX) % kYP, q = t / (kYP * kBX);
+          T* dst = buf + q * QS + part * kBYP * HXP + x;
+          T J = 0;
+#pragma unroll
+          for (int i = 1; i <= 2 * R; ++i) J += vr[j][i];
+#pragma unroll
+          for (int o = 0; o < kBYP - 1; ++o) dst[o * HXP] = trap_slide<R, T>(vr[j], o, J, inv_n);
+          dst[(kBYP - 1) * HXP] = trap_last<R, T>(vr[j], kBYP - 1, J, inv_n);
+        }
+      }
     }
     __syncthreads();
-    // ---- z pass and epilogue A (column threads)
-    const int slot = k % (2 * R);
+    // ---- z: advance the boxcars; the trapezoid of plane zo = za - R is their mean
     const bool full = k >= 2 * R;
-    T qb[10];
-    qb[0] = ring_push<R, T>(r0, Jz[0], yf[0 * kBN + col], slot, inv_n);
-    qb[1] = ring_push<R, T>(r1, Jz[1], yf[1 * kBN + col], slot, inv_n);
-    qb[2] = ring_push<R, T>(r2, Jz[2], yf[2 * kBN + col], slot, inv_n);
-    qb[3] = ring_push<R, T>(r3, Jz[3], yf[3 * kBN + col], slot, inv_n);
-    qb[4] = ring_push<R, T>(r4, Jz[4], yf[4 * kBN + col], slot, inv_n);
-    qb[5] = ring_push<R, T>(r5, Jz[5], yf[5 * kBN + col], slot, inv_n);
-    qb[6] = ring_push<R, T>(r6, Jz[6], yf[6 * kBN + col], slot, inv_n);
-    qb[7] = ring_push<R, T>(r7, Jz[7], yf[7 * kBN + col], slot, inv_n);
-    qb[8] = ring_push<R, T>(r8, Jz[8], yf[8 * kBN + col], slot, inv_n);
-    qb[9] = ring_push<R, T>(r9, Jz[9], yf[9 * kBN + col], slot, inv_n);
-    if (slot == 2 * R - 1) {
-      ring_reseed<R, T>(r0, Jz[0]);
-      ring_reseed<R, T>(r1, Jz[1]);
-      ring_reseed<R, T>(r2, Jz[2]);
-      ring_reseed<R, T>(r3, Jz[3]);
-      ring_reseed<R, T>(r4, Jz[4]);
-      ring_reseed<R, T>(r5, Jz[5]);
-      ring_reseed<R, T>(r6, Jz[6]);
-      ring_reseed<R, T>(r7, Jz[7]);
-      ring_reseed<R, T>(r8, Jz[8]);
-      ring_reseed<R, T>(r9, Jz[9]);
+    double qb[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const double prev = B[q];
+      B[q] = prev + (double)buf[q * QS + ycol];
+      qb[q] = (prev + B[q]) * inv_2n;
     }
     const int zo = za - R;
     const int us = (k - 2 * R + 3) % 3;
     float cur_rb = 1.f, cur_tau[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (full) {  // uniform
-      const T rinv = (T)1 / qb[0];
-      const T uT[3] = {qb[1] * rinv, qb[2] * rinv, qb[3] * rinv};
+      const double rinv = 1.0 / qb[0];
+      const double uT[3] = {qb[1] * rinv, qb[2] * rinv, qb[3] * rinv};
       cur_rb = (float)qb[0];
       // tau_ij = bar(rho u_i u_j) - bar(rho u_i) ut_j
       cur_tau[0] = (float)fma(-qb[1], uT[0], qb[4]);
@@ -261,8 +284,8 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         }
       }
     }
-    // every step: the ring reads of yf are done before the next staging overwrites it, and
-    // the velocity of plane zo is in LDS before the gradient reads it
+    // every step: the reads of the y-filtered plane are done before the next staging
+    // overwrites it, and the velocity of plane zo is in LDS before the gradient reads it
     __syncthreads();
     const int zg = zo - 1;
     if (k >= 2 * R + 1 && zg >= z0 && zg < z1) {  // uniform
@@ -294,7 +317,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
       }
       StatIn I;
       stat_inputs(lag_rb, u, lag_tau, P, interior, I);
-      accumulate_stats(I, acc);
+      stat_add(I, acc);
     }
     if (full) {
       lag_rb = cur_rb;
@@ -306,70 +329,67 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
 }
 
 template <int R, typename T>
-__global__ void __launch_bounds__(kBT) k_box1(FilterArgs A) {
+__global__ void __launch_bounds__(TileFor<R>::BT)
+    __attribute__((amdgpu_waves_per_eu(TileFor<R>::WAVES, TileFor<R>::WAVES)))
+    k_box1(FilterArgs A) {
   __shared__ double smem[BoxLds<R, T>::doubles];
   int widx, item;
   if (!map_block(A, widx, item)) return;
   box_body<R, T>(A, A.wa[widx], item, reinterpret_cast<unsigned char*>(smem));
 }
 
-constexpr int bmax(int a, int b) { return a > b ? a : b; }
+template <int R, typename T>
+BoxGeom geom_of() {
+  using C = TileFor<R>;
+  return BoxGeom{kBOX, C::BOY, C::BT, C::BT / 64, BoxLds<R, T>::blocks_per_cu};
+}
 
-// Box widths 2h, 4h, 8h, 16h in one launch: FP64 sums for the two narrow widths.
-__global__ void __launch_bounds__(kBT) k_box4(FilterArgs A) {
-  __shared__ double smem[bmax(bmax(BoxLds<1, double>::doubles, BoxLds<2, double>::doubles),
-                              bmax(BoxLds<4, float>::doubles, BoxLds<8, float>::doubles))];
-  int widx, item;
-  if (!map_block(A, widx, item)) return;
-  unsigned char* s = reinterpret_cast<unsigned char*>(smem);
-  switch (widx) {
-    case 0: box_body<1, double>(A, A.wa[0], item, s); break;
-    case 1: box_body<2, double>(A, A.wa[1], item, s); break;
-    case 2: box_body<4, float>(A, A.wa[2], item, s); break;
-    default: box_body<8, float>(A, A.wa[3], item, s); break;
+template <int R, typename T>
+hipError_t launch_of(const FilterArgs& a, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_box1<R, T>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
+  return hipGetLastError();
+}
+
+// Calls f.template operator()<R, T>() for a supported (radius, precision) pair.
+template <class F>
+bool dispatch(int R, int fp64, F&& f) {
+  if (fp64) {
+    switch (R) {
+      case 1: f.template operator()<1, double>(); return true;
+      case 2: f.template operator()<2, double>(); return true;
+      case 3: f.template operator()<3, double>(); return true;
+      case 4: f.template operator()<4, double>(); return true;
+      default: return false;
+    }
+  }
+  switch (R) {
+    case 1: f.template operator()<1, float>(); return true;
+    case 2: f.template operator()<2, float>(); return true;
+    case 3: f.template operator()<3, float>(); return true;
+    case 4: f.template operator()<4, float>(); return true;
+    case 5: f.template operator()<5, float>(); return true;
+    case 6: f.template operator()<6, float>(); return true;
+    case 7: f.template operator()<7, float>(); return true;
+    case 8: f.template operator()<8, float>(); return true;
+    default: return false;
   }
 }
 
 }  // namespace
 
-int box_tile_x() { return kBOX; }
-int box_tile_y() { return kBOY; }
-int box_stat_waves() { return kBT / 64; }
 bool box_supported(int R, int fp64) { return R >= 1 && (fp64 ? R <= 4 : R <= 8); }
 
-hipError_t launch_box(const FilterArgs& a, const int* radii, const int* fp64, int nblocks,
-                      hipStream_t s) {
-  const dim3 block(kBT), grid(nblocks);
-  if (a.nw == 4) {
-    if (!(radii[0] == 1 && radii[1] == 2 && radii[2] == 4 && radii[3] == 8 && fp64[0] &&
-          fp64[1] && !fp64[2] && !fp64[3]))
-      return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_box4, grid, block, 0, s, a);
-    return hipGetLastError();
-  }
+BoxGeom box_geometry(int R, int fp64) {
+  BoxGeom g{};
+  dispatch(R, fp64, [&]<int RR, typename T>() { g = geom_of<RR, T>(); });
+  return g;
+}
+
+hipError_t launch_box(const FilterArgs& a, int R, int fp64, int nblocks, hipStream_t s) {
   if (a.nw != 1) return hipErrorInvalidValue;
-  if (fp64[0]) {
-    switch (radii[0]) {
-      case 1: hipLaunchKernelGGL((k_box1<1, double>), grid, block, 0, s, a); break;
-      case 2: hipLaunchKernelGGL((k_box1<2, double>), grid, block, 0, s, a); break;
-      case 3: hipLaunchKernelGGL((k_box1<3, double>), grid, block, 0, s, a); break;
-      case 4: hipLaunchKernelGGL((k_box1<4, double>), grid, block, 0, s, a); break;
-      default: return hipErrorInvalidValue;
-    }
-  } else {
-    switch (radii[0]) {
-      case 1: hipLaunchKernelGGL((k_box1<1, float>), grid, block, 0, s, a); break;
-      case 2: hipLaunchKernelGGL((k_box1<2, float>), grid, block, 0, s, a); break;
-      case 3: hipLaunchKernelGGL((k_box1<3, float>), grid, block, 0, s, a); break;
-      case 4: hipLaunchKernelGGL((k_box1<4, float>), grid, block, 0, s, a); break;
-      case 5: hipLaunchKernelGGL((k_box1<5, float>), grid, block, 0, s, a); break;
-      case 6: hipLaunchKernelGGL((k_box1<6, float>), grid, block, 0, s, a); break;
-      case 7: hipLaunchKernelGGL((k_box1<7, float>), grid, block, 0, s, a); break;
-      case 8: hipLaunchKernelGGL((k_box1<8, float>), grid, block, 0, s, a); break;
-      default: return hipErrorInvalidValue;
-    }
-  }
-  return hipGetLastError();
+  hipError_t e = hipErrorInvalidValue;
+  dispatch(R, fp64, [&]<int RR, typename T>() { e = launch_of<RR, T>(a, nblocks, s); });
+  return e;
 }
 
 }  // namespace kcf

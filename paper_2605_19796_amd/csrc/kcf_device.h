@@ -60,8 +60,10 @@ __device__ __forceinline__ void point_closures(const WidthArgs& W, float rb, con
   P.omt = 1.f / (fmaxf(W.nu_mol, P.nut) * W.inv_theta + W.half_dt);
 }
 
-// Contribution of one point to FP64 sum slot s. Products of two float32 values are exact
-// in double, so every contribution is computed in double from the stored float outputs.
+// What one point contributes to the FP64 sums. Products of two float32 values are exact in
+// double, so every contribution is formed in double from the stored float outputs. Points
+// outside the interior or with a non-finite value contribute zeros: their inputs are replaced
+// by zero here, before any product is formed, so no NaN reaches a sum.
 struct StatIn {
   float rb, tau[6], tgm[6];
   double ke, pi, pigm, pism;
@@ -86,87 +88,117 @@ __device__ __forceinline__ void stat_inputs(float rb, const float (&u)[3], const
   bool fin = isfinite(pi) && isfinite(pigm) && isfinite(pism) && isfinite(ke) && isfinite(rb);
 #pragma unroll
   for (int s = 0; s < 6; ++s) fin = fin && isfinite(tau[s]) && isfinite(P.tgm[s]);
+  const bool use = valid && fin;
   I.bad = valid && !fin;
-  I.use = valid && fin;
-  I.rb = rb;
-  I.ke = ke;
-  I.pi = pi;
-  I.pigm = pigm;
-  I.pism = pism;
+  I.use = use;
+  I.rb = use ? rb : 0.f;
+  I.ke = use ? ke : 0.0;
+  I.pi = use ? pi : 0.0;
+  I.pigm = use ? pigm : 0.0;
+  I.pism = use ? pism : 0.0;
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
-    I.tau[s] = tau[s];
-    I.tgm[s] = P.tgm[s];
+    I.tau[s] = use ? tau[s] : 0.f;
+    I.tgm[s] = use ? P.tgm[s] : 0.f;
   }
 }
 
-__device__ __forceinline__ double stat_raw(const StatIn& I, int s) {
-  if (s == S_N) return 1.0;
+// Contribution to slot s (s is a compile-time constant after unrolling).
+__device__ __forceinline__ double stat_val(const StatIn& I, int s) {
+  if (s == S_N) return I.use ? 1.0 : 0.0;
+  if (s == S_NONFINITE) return I.bad ? 1.0 : 0.0;
   if (s == S_RHO) return (double)I.rb;
   if (s == S_KE) return I.ke;
   if (s == S_PI) return I.pi;
   if (s == S_PIGM) return I.pigm;
+  if (s == S_PISM) return I.pism;
   if (s == S_PI2) return I.pi * I.pi;
   if (s == S_PIGM2) return I.pigm * I.pigm;
   if (s == S_PIPIGM) return I.pi * I.pigm;
   if (s >= S_TAU && s < S_TAU + 6) return (double)I.tau[s - S_TAU];
   if (s >= S_TGM && s < S_TGM + 6) return (double)I.tgm[s - S_TGM];
-  if (s >= S_TAU2 && s < S_TAU2 + 6) return (double)I.tau[s - S_TAU2] * (double)I.tau[s - S_TAU2];
-  if (s >= S_TGM2 && s < S_TGM2 + 6) return (double)I.tgm[s - S_TGM2] * (double)I.tgm[s - S_TGM2];
-  if (s >= S_TAUTGM && s < S_TAUTGM + 6)
-    return (double)I.tau[s - S_TAUTGM] * (double)I.tgm[s - S_TAUTGM];
-  return I.pism;  // S_PISM
+  if (s >= S_TAU2 && s < S_TAU2 + 6) {
+    const double t = I.tau[s - S_TAU2];
+    return t * t;
+  }
+  if (s >= S_TGM2 && s < S_TGM2 + 6) {
+    const double g = I.tgm[s - S_TGM2];
+    return g * g;
+  }
+  const double t = I.tau[s - S_TAUTGM], g = I.tgm[s - S_TAUTGM];
+  return t * g;  // S_TAUTGM
 }
 
-__device__ __forceinline__ double stat_value(const StatIn& I, int s) {
-  if (s == S_NONFINITE) return I.bad ? 1.0 : 0.0;
-  return I.use ? stat_raw(I, s) : 0.0;
+// ---- FP64 statistics: per-point contributions folded over the wave with lane swaps
+//
+// A point's 40 contributions are reduced over the wave in two swap-and-add steps that use
+// the row-swap permutes of gfx950 (lanes L and L ^ 32, then L and L ^ 16): afterwards lane
+// L holds the 4-lane sums of slots 10 * (2 * b5 + b4) + k, k < 10, where b5 and b4 are bits
+// 5 and 4 of L. These ten values are accumulated per lane across every point the thread
+// visits, and the remaining 16-lane reduction runs once, when the block writes its record.
+// The order of every addition is fixed, so the totals do not depend on timing. All 64 lanes
+// of the wave must be active wherever these helpers run.
+
+struct StatAcc {
+  double s[10];
+};
+
+__device__ __forceinline__ void stat_zero(StatAcc& a) {
+#pragma unroll
+  for (int k = 0; k < 10; ++k) a.s[k] = 0.0;
 }
 
-// Reduce 8 per-lane values over the wave: afterwards every lane holds the wave total of
-// slot (lane >> 3). Fixed order: the result does not depend on timing.
-__device__ __forceinline__ double wave_reduce8(double (&v)[8]) {
+// x from this lane and the partner's copy of the value it does not keep: lanes in the lower
+// half of each pair keep x (their own plus the partner's x), the upper half keep y.
+template <int Span>
+__device__ __forceinline__ double swap_add(double x, double y) {
+  const unsigned long long xb = __double_as_longlong(x), yb = __double_as_longlong(y);
+  const unsigned xl = (unsigned)xb, xh = (unsigned)(xb >> 32);
+  const unsigned yl = (unsigned)yb, yh = (unsigned)(yb >> 32);
+  unsigned nxl, nxh, nyl, nyh;
+  if constexpr (Span == 32) {
+    const auto lo = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+    nxl = lo[0], nyl = lo[1], nxh = hi[0], nyh = hi[1];
+  } else {
+    const auto lo = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    nxl = lo[0], nyl = lo[1], nxh = hi[0], nyh = hi[1];
+  }
+  const double nx = __longlong_as_double((long long)(((unsigned long long)nxh << 32) | nxl));
+  const double ny = __longlong_as_double((long long)(((unsigned long long)nyh << 32) | nyl));
+  return nx + ny;
+}
+
+// Slots are folded in the order k, k + 20 (first swap) and k, k + 10 (second swap), one
+// accumulator at a time, so that only a few contributions are live at once.
+__device__ __forceinline__ void stat_add(const StatIn& I, StatAcc& a) {
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    const double lo = swap_add<32>(stat_val(I, k), stat_val(I, k + 20));
+    const double hi = swap_add<32>(stat_val(I, k + 10), stat_val(I, k + 30));
+    a.s[k] += swap_add<16>(lo, hi);
+  }
+}
+
+// Wave totals: the 16-lane reduction of every accumulator, then lanes 0, 16, 32 and 48
+// write their ten slots of the wave's 40-slot record.
+__device__ __forceinline__ void write_stats(double* part, const StatAcc& a) {
   const int lane = __lane_id();
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  double t[10];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const double send = b5 ? v[s] : v[s + 4];
-    const double keep = b5 ? v[s + 4] : v[s];
-    v[s] = keep + __shfl_xor(send, 32);
+  for (int k = 0; k < 10; ++k) {
+    double r = a.s[k];
+    r += __shfl_xor(r, 8);
+    r += __shfl_xor(r, 4);
+    r += __shfl_xor(r, 2);
+    r += __shfl_xor(r, 1);
+    t[k] = r;
   }
+  if ((lane & 15) == 0) {
+    const int g = 2 * (lane >> 5) + ((lane >> 4) & 1);
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const double send = b4 ? v[s] : v[s + 2];
-    const double keep = b4 ? v[s + 2] : v[s];
-    v[s] = keep + __shfl_xor(send, 16);
-  }
-  {
-    const double send = b3 ? v[0] : v[1];
-    const double keep = b3 ? v[1] : v[0];
-    v[0] = keep + __shfl_xor(send, 8);
-  }
-  double r = v[0];
-  r += __shfl_xor(r, 4);
-  r += __shfl_xor(r, 2);
-  r += __shfl_xor(r, 1);
-  return r;
-}
-
-__device__ __forceinline__ void accumulate_stats(const StatIn& I, double (&acc)[5]) {
-#pragma unroll
-  for (int g = 0; g < 5; ++g) {
-    double v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = stat_value(I, g * 8 + j);
-    acc[g] += wave_reduce8(v);
-  }
-}
-
-__device__ __forceinline__ void write_stats(double* part, const double (&acc)[5]) {
-  const int lane = __lane_id();
-  if ((lane & 7) == 0) {
-#pragma unroll
-    for (int g = 0; g < 5; ++g) part[g * 8 + (lane >> 3)] = acc[g];
+    for (int k = 0; k < 10; ++k) part[10 * g + k] = t[k];
   }
 }
 

@@ -150,7 +150,8 @@ __device__ __forceinline__ void filter_body(const FilterArgs& A, const WidthArgs
   for (int j = 0; j < 5; ++j)
 #pragma unroll
     for (int t = 0; t < D; ++t) ring[j][t] = 0;
-  double acc[5] = {0, 0, 0, 0, 0};
+  StatAcc acc;
+  stat_zero(acc);
 
   for (int k = 0; k < nsteps; ++k) {
     const int za = za0 + k;
@@ -296,7 +297,7 @@ __device__ __forceinline__ void filter_body(const FilterArgs& A, const WidthArgs
       if (stat_wave) {
         StatIn I;
         stat_inputs(rb, u, tau, P, valid, I);
-        accumulate_stats(I, acc);
+        stat_add(I, acc);
       }
     }
   }
@@ -336,7 +337,8 @@ constexpr int kCT = 256;
 
 __global__ void __launch_bounds__(kCT) k_grad_closure(ClosureArgs C) {
   const WidthArgs& W = C.wa;
-  double acc[5] = {0, 0, 0, 0, 0};
+  StatAcc acc;
+  stat_zero(acc);
   const int64_t plane = (int64_t)C.nx * C.ny;
   const int64_t stride = (int64_t)gridDim.x * kCT;
   // all lanes run the same trip count so the wave reductions stay converged
@@ -385,7 +387,7 @@ __global__ void __launch_bounds__(kCT) k_grad_closure(ClosureArgs C) {
     if (W.partials) {
       StatIn I;
       stat_inputs(rb, u, tau, P, valid, I);
-      accumulate_stats(I, acc);
+      stat_add(I, acc);
     }
   }
   if (W.partials)

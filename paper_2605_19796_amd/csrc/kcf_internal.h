@@ -92,11 +92,14 @@ hipError_t launch_reduce_check(const float* a, const float* b, int64_t n, double
 int kernel_radius_for(int r);   // radius of the kernel instance used for stencil radius r
 
 // box kernels (kcf_box.hip)
-int box_tile_x();
-int box_tile_y();
-int box_stat_waves();
+struct BoxGeom {
+  int tile_x, tile_y;  // output columns of a tile
+  int threads;         // threads per workgroup
+  int stat_waves;      // per-wave statistics records per (tile, z-chunk) item
+  int blocks_per_cu;   // resident workgroups per CU
+};
 bool box_supported(int R, int fp64);
-hipError_t launch_box(const FilterArgs& a, const int* radii, const int* fp64, int nblocks,
-                      hipStream_t s);
+BoxGeom box_geometry(int R, int fp64);
+hipError_t launch_box(const FilterArgs& a, int R, int fp64, int nblocks, hipStream_t s);
 
 }  // namespace kcf

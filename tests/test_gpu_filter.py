@@ -8,6 +8,7 @@ they agree to the field tolerance.
 """
 import math
 import sys
+import zlib
 
 import numpy as np
 import pytest
@@ -80,12 +81,17 @@ def check_fields(gpu, ora, tol=TOL, fields=ALL):
 
 
 def check_stats(st, o, tol=1e-5):
+    """Width statistics against the oracle's. Pi = -<tau:S> can cancel to far below its terms
+    (random fields), and the device forms it from float32 tau and G, so its error is bounded
+    relative to the mean absolute term <sum |tau_ij S_ij|>, not to |Pi|."""
     os_ = o["stats"]
     assert st["n_nonfinite"] == 0
     assert abs(st["mean_rho_bar"] - os_["mean_rho_bar"]) <= 1e-6 * abs(os_["mean_rho_bar"])
     assert abs(st["ke_resolved"] - os_["ke_resolved"]) <= tol * abs(os_["ke_resolved"])
-    assert abs(st["pi"] - os_["pi"]) <= tol * abs(os_["pi"]) + 1e-12
-    assert abs(st["pi_gm"] - os_["pi_gm"]) <= tol * abs(os_["pi_gm"]) + 1e-12
+    S, _ = F.strain_rotation(o["G"])
+    for key, t in (("pi", o["tau"]), ("pi_gm", o["tau_gm"])):
+        scale = float(np.mean(np.sum(np.abs(t * S), axis=(0, 1))))
+        assert abs(st[key] - os_[key]) <= tol * scale, (key, st[key], os_[key], scale)
     for c in range(6):
         assert abs(st["corr_tau_gm"][c] - os_["corr_tau_gm"][c]) <= 1e-4, (c, st["corr_tau_gm"], os_["corr_tau_gm"])
     assert abs(st["corr_pi"] - os_["corr_pi"]) <= 1e-4
@@ -110,7 +116,7 @@ def test_full_field_parity(ctx, name, shape, kind, nd):
         rho, u = rho.numpy(), u.numpy()
         h = 2 * math.pi / 32
     else:
-        rho, u = synth.random_fields(shape, seed=hash(name) % 1000)
+        rho, u = synth.random_fields(shape, seed=zlib.crc32(name.encode()) % 1000)
         h = 0.1
     gpu, st = run_gpu(ctx, rho, u, h, [(kind, nd)])
     ora = F.full_path(rho, u, kind, nd, h)
