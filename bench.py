@@ -1,17 +1,23 @@
 """Throughput of the filtering path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-learned]
 
 Workload: 512^3 periodic grid of synthetic spectral turbulence (u_rms 0.3, k0 16,
-rho = 1 + 0.2 s), FP32 fields resident in HBM; one step = one fused pass computing four
-box-filter widths (2h, 4h, 8h, 16h): products, separable periodic filter, Favre velocity,
-SGS stress tau (all written), central-difference gradient, gradient-model and Smagorinsky
-closures and kinetic-closure scalars (on chip), FP64 statistics per width (SGS dissipation,
-tau-closure correlations) read back to the host, plus the input's E_k and enstrophy.
+rho = 1 + 0.2 s), FP32 fields resident in HBM; one step = four box-filter widths (2h, 4h,
+8h, 16h), one kernel launch each, every launch computing: products, separable periodic
+filter, Favre velocity, SGS stress tau (all written), central-difference gradient,
+gradient-model and Smagorinsky closures (on chip), FP64 statistics per width (SGS
+dissipation, tau-closure correlations) read back to the host; plus the input's E_k and
+enstrophy.
 
 Prints one JSON line. `value` is grid points per second (each point filtered at all four
-widths). `roofline` is for the fused filter kernel: algorithmic bytes (inputs 16 B +
-outputs 4 x 40 B per point) over its HIP-event time on the stream it runs on.
+widths). `roofline` is for the kernel with the largest share of the step: algorithmic bytes
+of one launch (inputs 16 B + outputs 40 B per point) over its average HIP-event time on the
+stream it runs on.
+
+Profiling modes (for rocprofv3 runs): --profile-run times a few steps and skips the CPU
+baseline and the learned section; --copy-calibration runs only a plain device copy of known
+size, against which the HBM byte counters are scaled.
 """
 from __future__ import annotations
 
@@ -27,20 +33,31 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_POINT = 16 + 4 * 40  # read rho,u; write rho_bar, ut, tau per width
-KERNEL = "k_filter_box4"
+BYTES_PER_POINT = 16 + 40  # one width: read rho, u; write rho_bar, ut, tau
 WIDTHS = (2, 4, 8, 16)
+# kernel instance of each width (radius n/2; FP64 sums up to 4h)
+KERNELS = {2: "k_box1<1, double>", 4: "k_box1<2, double>", 8: "k_box1<4, float>",
+           16: "k_box1<8, float>"}
+KERNEL_SOURCES = ("kcf_box.hip", "kcf_device.h", "kcf_internal.h")
+COPY_BYTES = 1 << 31  # plain copy for counter calibration: 2 GiB read, 2 GiB written
 
 
 def kernel_source_hash():
-    p = os.path.join(ROOT, "paper_2605_19796_amd", "csrc", "kcf_filter.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2605_19796_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source; otherwise None."""
-    p = os.path.join(ROOT, "profiles", "k_filter_box4_512_traffic.json")
+def traffic_file(kernel):
+    tag = kernel.replace("<", "_").replace(">", "").replace(", ", "_").replace(" ", "")
+    return os.path.join(ROOT, "profiles", f"{tag}_512_traffic.json")
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; otherwise None."""
+    p = traffic_file(kernel)
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
@@ -159,6 +176,18 @@ def learned_section(ctx, args):
     return out
 
 
+def copy_calibration():
+    """One plain device-to-device copy of COPY_BYTES, for scaling FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = COPY_BYTES // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,13 +196,21 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="a few steps only (no CPU baseline, no learned section)")
+    ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--learned-n", type=int, default=1024, help="grid of the learned-vs-plain race")
     ap.add_argument("--train-steps", type=int, default=3000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the filtering path here is a single-GPU build "
-              "(see DESIGN.md for how it would shard); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the filtering path here is a single-GPU build; "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.profile_run:
+        args.no_cpu_baseline = args.no_learned = True
 
     import torch
     from paper_2605_19796_amd import kcf, synth
@@ -192,7 +229,7 @@ def main():
         ist = ctx.input_stats(rho, u, h)
         return st, ist
 
-    progress(f"{n}^3 fused 4-width pass: warmup")
+    progress(f"{n}^3 4-width pass: warmup")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -203,15 +240,22 @@ def main():
         st, ist = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kms, launches = ctx.kernel_ms()
+    times = ctx.kernel_times()
     ctx.enable_timing(False)
+    progress(f"timed {args.steps} steps")
 
     ms_step = (t1 - t0) * 1e3 / args.steps
     pts = float(n) ** 3
     value = pts / (ms_step * 1e-3)
-    k_avg_ms = kms / max(launches, 1)
-    achieved = BYTES_PER_POINT * pts / (k_avg_ms * 1e-3) / 1e9
-    traffic = load_traffic()
+    # the timed launches are the filter kernels, one per width per step, in width order
+    assert len(times) == len(WIDTHS) * args.steps, (len(times), args.steps)
+    per_width = {w: times[i::len(WIDTHS)] for i, w in enumerate(WIDTHS)}
+    avg = {w: sum(v) / len(v) for w, v in per_width.items()}
+    dom = max(WIDTHS, key=lambda w: avg[w])
+    kernel = KERNELS[dom]
+    bytes_launch = BYTES_PER_POINT * pts
+    achieved = bytes_launch / (avg[dom] * 1e-3) / 1e9
+    traffic = load_traffic(kernel)
     line = {
         "metric": "filtered grid points/s (% HBM roofline); learned vs plain closure at fixed error",
         "value": value,
@@ -226,15 +270,17 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{n}^3 periodic spectral turbulence, box filter widths 2h/4h/8h/16h in one "
-                        "fused pass, FP32 fields, FP64 on-GPU statistics",
+            "workload": f"{n}^3 periodic spectral turbulence, box filter widths 2h/4h/8h/16h, "
+                        "FP32 fields, FP64 on-GPU statistics",
             "grid": n, "filter": "box", "widths_h": list(WIDTHS), "k0": 16 * n / 512,
             "u_rms": 0.3, "rho_amp": 0.2, "seeds": [1004, 2004],
         },
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": KERNEL, "kernel_ms": k_avg_ms, "bytes_per_point": BYTES_PER_POINT,
+            "kernel": kernel, "width_h": dom, "kernel_ms": avg[dom],
+            "bytes_per_launch": bytes_launch, "bytes_per_point": BYTES_PER_POINT,
+            "kernel_ms_by_width": {f"{w}h": avg[w] for w in WIDTHS},
         },
         "stats": {
             f"{w}h": {"pi": s["pi"], "pi_gm": s["pi_gm"], "corr_tau_gm": s["corr_tau_gm"],

@@ -128,6 +128,10 @@ const char *kcf_last_error(void);
  * the last reset (and the number of launches) after synchronising the stream. */
 int kcf_ctx_enable_timing(kcf_ctx *ctx, int on);
 int kcf_ctx_kernel_ms(kcf_ctx *ctx, double *ms, int *launches);
+/* The same record launch by launch: ms[i] (host, cap entries) is the time of the i-th timed
+ * launch since the last reset, in launch order (a call of kcf_filter_favre launches one
+ * kernel per width, in the order of its filters). KCF_EINVAL if cap is too small. Resets. */
+int kcf_ctx_kernel_times(kcf_ctx *ctx, float *ms, int cap, int *launches);
 
 /* ---- host helper (no GPU) ------------------------------------------------------------ */
 /* 1-D taps w_{-R..R} of the filter used by the GPU (float32), its radius R and the second
@@ -138,12 +142,14 @@ int kcf_filter_taps(int kind, int delta_over_h, double h, float *w, int cap, int
                     double *m2);
 
 /* ---- the filtering path --------------------------------------------------------------- */
-/* For each of n_filters (1..4) widths, in one pass over rho (N) and u (3N):
+/* For each of n_filters (1..4) widths, one kernel launch, in one pass over rho (N) and u (3N):
  * products rho, rho u_i, rho u_i u_j; separable periodic filter; Favre division;
  * tau; central-difference gradient of ut; closures; FP64 statistics.
- * outs[f] selects the fields written for width f (NULL members are skipped; gradient,
- * closures and statistics are computed on chip either way). stats may be NULL; when given
- * it has n_filters entries and the call synchronises the stream.
+ * outs[f] selects the fields written for width f (NULL members are skipped). stats may be
+ * NULL; when given it has n_filters entries, the gradient, both closures and the statistics
+ * are evaluated on chip, and the call synchronises the stream. Without stats the gradient
+ * and closures are evaluated only for the fields outs[f] asks for (none for rho_bar, ut and
+ * tau alone).
  * Errors: KCF_EINVAL for null rho/u/outs/grid, n < 3 in any direction, n_filters outside
  * 1..4, bad filter kind or width; KCF_EUNSUPPORTED when 2R+1 exceeds a grid dimension or
  * R > 12. */

@@ -270,6 +270,18 @@ int kcf_ctx_enable_timing(kcf_ctx* c, int on) {
   return KCF_OK;
 }
 
+int kcf_ctx_kernel_times(kcf_ctx* c, float* ms, int cap, int* launches) {
+  if (!c || !ms || !launches) return fail(KCF_EINVAL, "NULL argument");
+  const int n = (int)(c->ev_used / 2);
+  if (n > cap) return fail(KCF_EINVAL, "ms holds fewer entries than timed launches");
+  KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  for (int i = 0; i < n; ++i)
+    KCF_HIP(hipEventElapsedTime(&ms[i], c->ev[2 * i], c->ev[2 * i + 1]), "hipEventElapsedTime");
+  *launches = n;
+  c->ev_used = 0;
+  return KCF_OK;
+}
+
 int kcf_ctx_kernel_ms(kcf_ctx* c, double* ms, int* launches) {
   if (!c || !ms) return fail(KCF_EINVAL, "NULL argument");
   KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
@@ -348,6 +360,7 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     A.zlen = (grid->nz + A.nzc - 1) / A.nzc;
     A.nzc = (grid->nz + A.zlen - 1) / A.zlen;
     A.tiles_per_xcd = (A.ntiles * A.nzc + 7) / 8;
+    A.strip_w = box ? bg.strip_w : 0;
     A.nw = 1;
   };
   // partial sums: [width][items][waves][kNStat]
@@ -364,7 +377,7 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
       part_off[f] = off;
       off += part_width[f];
     }
-    if ((rc = ensure_partials(c, off))) return rc;
+    if (stats && (rc = ensure_partials(c, off))) return rc;
   }
   auto fill_width = [&](WidthArgs& W, int f, int K) {
     std::memset(&W, 0, sizeof(W));
@@ -376,7 +389,7 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     }
     set_outputs(W, &outs[f]);
     set_closure(W, cp, filters[f].delta_over_h * grid->h, taps[f].m2);
-    W.partials = c->d_part + part_off[f];
+    W.partials = stats ? c->d_part + part_off[f] : nullptr;
   };
   for (int f = 0; f < nf; ++f) {
     FilterArgs A;

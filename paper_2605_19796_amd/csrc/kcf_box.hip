@@ -35,7 +35,7 @@ constexpr int kLdsPerCU = 160 * 1024;
 // Tile and workgroup shape. Narrow windows use short tiles (18x14 columns, 256 threads) so
 // that three workgroups share a CU; wide windows use tall tiles (18x28, 512 threads), where
 // the 2R-cell halo of a short tile would cost more than the lost occupancy.
-template <int BY_, int BT_, int WAVES_>
+template <int BY_, int BT_, int WAVES_, int STRIP_>
 struct BoxCfg {
   static constexpr int BY = BY_;         // computed rows
   static constexpr int BOY = BY - 2;     // output rows
@@ -44,10 +44,11 @@ struct BoxCfg {
   static constexpr int WAVES = WAVES_;   // waves per SIMD the register budget allows
   static constexpr int YP = BT >= 512 ? 2 : 1;  // y-pass tasks per (quantity, column)
   static constexpr int BYP = BY / YP;    // rows per y-pass task
+  static constexpr int STRIP = STRIP_;   // tile numbering in strips this wide (0: rows)
   static_assert(BN <= BT && BY % YP == 0 && BT % 64 == 0, "tile does not fit the workgroup");
 };
-using ShortTile = BoxCfg<14, 256, 3>;
-using TallTile = BoxCfg<28, 512, 2>;
+using ShortTile = BoxCfg<14, 256, 3, 0>;
+using TallTile = BoxCfg<28, 512, 2, 8>;
 template <int R>
 using TileFor = typename std::conditional<(R <= 4), ShortTile, TallTile>::type;
 
@@ -119,7 +120,8 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   const int tid = threadIdx.x;
   const int tile = item % A.ntiles;
   const int zc = item / A.ntiles;
-  const int tx = tile % A.ntx, ty = tile / A.ntx;
+  int tx, ty;
+  tile_coords(A, tile, tx, ty);
   const int x0 = tx * kBOX - 1, y0 = ty * kBOY - 1;  // global coordinates of column (0, 0)
   const int z0 = zc * A.zlen;
   const int z1 = min(z0 + A.zlen, A.nz);
@@ -172,6 +174,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   float lag_rb = 1.f, lag_tau[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   StatAcc acc;
   stat_zero(acc);
+  const bool need_grad = needs_gradient(W);
 
   for (int k = 0; k < nsteps; ++k) {
     const int za = za0 + k;
@@ -288,7 +291,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
     // overwrites it, and the velocity of plane zo is in LDS before the gradient reads it
     __syncthreads();
     const int zg = zo - 1;
-    if (k >= 2 * R + 1 && zg >= z0 && zg < z1) {  // uniform
+    if (need_grad && k >= 2 * R + 1 && zg >= z0 && zg < z1) {  // uniform
       // ---- epilogue B: gradient, closures, statistics of plane zg
       const int sg = (us + 2) % 3, sm = (us + 1) % 3, sp = us;
       PointOut P;
@@ -315,9 +318,11 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         for (int s = 0; s < 6; ++s) P.tgm[s] = P.tsm[s] = 0.f;
         P.ksgs = P.nut = P.omt = 0.f;
       }
-      StatIn I;
-      stat_inputs(lag_rb, u, lag_tau, P, interior, I);
-      stat_add(I, acc);
+      if (W.partials) {  // uniform
+        StatIn I;
+        stat_inputs(lag_rb, u, lag_tau, P, interior, I);
+        stat_add(I, acc);
+      }
     }
     if (full) {
       lag_rb = cur_rb;
@@ -325,7 +330,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
       for (int s = 0; s < 6; ++s) lag_tau[s] = cur_tau[s];
     }
   }
-  write_stats(W.partials + ((int64_t)item * (kBT / 64) + (tid >> 6)) * kNStat, acc);
+  if (W.partials) write_stats(W.partials + ((int64_t)item * (kBT / 64) + (tid >> 6)) * kNStat, acc);
 }
 
 template <int R, typename T>
@@ -341,7 +346,7 @@ __global__ void __launch_bounds__(TileFor<R>::BT)
 template <int R, typename T>
 BoxGeom geom_of() {
   using C = TileFor<R>;
-  return BoxGeom{kBOX, C::BOY, C::BT, C::BT / 64, BoxLds<R, T>::blocks_per_cu};
+  return BoxGeom{kBOX, C::BOY, C::BT, C::BT / 64, BoxLds<R, T>::blocks_per_cu, C::STRIP};
 }
 
 template <int R, typename T>

@@ -20,8 +20,9 @@ struct PointOut {
   float ksgs, nut, omt;
 };
 
-__device__ __forceinline__ void point_closures(const WidthArgs& W, float rb, const float (&tau)[6],
-                                               PointOut& P) {
+// Gradient model rho_bar C M2 (G G^T)_ij (gm_form 0) or the transposed contraction
+// (G^T G)_ij (gm_form 1); gm_coef holds C M2.
+__device__ __forceinline__ void gm_closure(const WidthArgs& W, float rb, PointOut& P) {
   const float(&G)[3][3] = P.G;
   float c = W.gm_coef * rb;
   const int ii[6] = {0, 0, 0, 1, 1, 2};
@@ -36,6 +37,13 @@ __device__ __forceinline__ void point_closures(const WidthArgs& W, float rb, con
       a = G[0][i] * G[0][j] + G[1][i] * G[1][j] + G[2][i] * G[2][j];
     P.tgm[s] = c * a;
   }
+}
+
+// Smagorinsky -2 rho_bar (C_s Delta)^2 |S| S^d; smag_coef holds (C_s Delta)^2.
+__device__ __forceinline__ void smag_closure(const WidthArgs& W, float rb, PointOut& P) {
+  const float(&G)[3][3] = P.G;
+  const int ii[6] = {0, 0, 0, 1, 1, 2};
+  const int jj[6] = {0, 1, 2, 1, 2, 2};
   float S[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -54,10 +62,28 @@ __device__ __forceinline__ void point_closures(const WidthArgs& W, float rb, con
     const int i = ii[s], j = jj[s];
     P.tsm[s] = cs * (S[i][j] - (i == j ? trs : 0.f));
   }
-  const float rref = W.ksgs_rho_ref ? 1.f : rb;
-  P.ksgs = fabsf(tau[0] + tau[3] + tau[5]) / (2.f * rref);
-  P.nut = W.cnu_delta * sqrtf(P.ksgs);
-  P.omt = 1.f / (fmaxf(W.nu_mol, P.nut) * W.inv_theta + W.half_dt);
+}
+
+// Closures of one point from its gradient (in P.G), filtered density and tau. Only what is
+// stored or reduced is evaluated; the rest is left at zero.
+__device__ __forceinline__ void point_closures(const WidthArgs& W, float rb, const float (&tau)[6],
+                                               PointOut& P) {
+  const bool stats = W.partials != nullptr;  // the statistics need both closures
+#pragma unroll
+  for (int s = 0; s < 6; ++s) P.tgm[s] = P.tsm[s] = 0.f;
+  P.ksgs = P.nut = P.omt = 0.f;
+  if (stats || W.tau_gm) {  // uniform
+    gm_closure(W, rb, P);
+  }
+  if (stats || W.tau_smag) {  // uniform
+    smag_closure(W, rb, P);
+  }
+  if (W.k_sgs || W.nu_t || W.omega_t) {  // uniform; only stored, never reduced
+    const float rref = W.ksgs_rho_ref ? 1.f : rb;
+    P.ksgs = fabsf(tau[0] + tau[3] + tau[5]) / (2.f * rref);
+    P.nut = W.cnu_delta * sqrtf(P.ksgs);
+    P.omt = 1.f / (fmaxf(W.nu_mol, P.nut) * W.inv_theta + W.half_dt);
+  }
 }
 
 // What one point contributes to the FP64 sums. Products of two float32 values are exact in
@@ -85,9 +111,10 @@ __device__ __forceinline__ void stat_inputs(float rb, const float (&u)[3], const
   }
   const double ke = 0.5 * (double)rb *
                     ((double)u[0] * u[0] + (double)u[1] * u[1] + (double)u[2] * u[2]);
-  bool fin = isfinite(pi) && isfinite(pigm) && isfinite(pism) && isfinite(ke) && isfinite(rb);
-#pragma unroll
-  for (int s = 0; s < 6; ++s) fin = fin && isfinite(tau[s]) && isfinite(P.tgm[s]);
+  // Every input reaches one of these four sums through a product (a NaN or an infinity stays
+  // non-finite, also when multiplied by zero), and sums of products of float32 values cannot
+  // overflow in double, so one test on their total covers the point.
+  const bool fin = isfinite(pi + pigm + pism + ke);
   const bool use = valid && fin;
   I.bad = valid && !fin;
   I.use = use;
@@ -202,6 +229,11 @@ __device__ __forceinline__ void write_stats(double* part, const StatAcc& a) {
   }
 }
 
+// Whether the gradient epilogue has anything to produce (uniform over the launch).
+__device__ __forceinline__ bool needs_gradient(const WidthArgs& W) {
+  return W.partials || W.grad || W.tau_gm || W.tau_smag || W.k_sgs || W.nu_t || W.omega_t;
+}
+
 __device__ __forceinline__ void store_point(const WidthArgs& W, int64_t g, int64_t ntot,
                                             const PointOut& P) {
   if (W.grad) {
@@ -221,6 +253,31 @@ __device__ __forceinline__ void store_point(const WidthArgs& W, int64_t g, int64
   if (W.k_sgs) W.k_sgs[g] = P.ksgs;
   if (W.nu_t) W.nu_t[g] = P.nut;
   if (W.omega_t) W.omega_t[g] = P.omt;
+}
+
+// Tile t of a z-chunk -> tile coordinates. With strip_w > 0 tiles are numbered in vertical
+// strips strip_w tiles wide, row by row inside a strip, so that the workgroups an XCD runs at
+// the same time cover a compact patch and share their halos in L2 (tall tiles); otherwise in
+// plain rows.
+__device__ __forceinline__ void tile_coords(const FilterArgs& A, int t, int& tx, int& ty) {
+  const int sw = A.strip_w;
+  if (sw <= 0 || sw >= A.ntx) {
+    tx = t % A.ntx;
+    ty = t / A.ntx;
+    return;
+  }
+  const int full = A.ntx / sw;  // strips of full width
+  const int per_strip = sw * A.nty;
+  if (t < full * per_strip) {
+    const int s = t / per_strip, r = t % per_strip;
+    tx = s * sw + r % sw;
+    ty = r / sw;
+  } else {
+    const int w = A.ntx - full * sw;  // the last, narrower strip
+    const int r = t - full * per_strip;
+    tx = full * sw + r % w;
+    ty = r / w;
+  }
 }
 
 // XCD-aware block mapping: consecutive block ids go to different XCDs, so block L is

@@ -98,7 +98,8 @@ __device__ __forceinline__ void filter_body(const FilterArgs& A, const WidthArgs
   const int tid = threadIdx.x;
   const int tile = item % A.ntiles;
   const int zc = item / A.ntiles;
-  const int tx = tile % A.ntx, ty = tile / A.ntx;
+  int tx, ty;
+  tile_coords(A, tile, tx, ty);
   const int x0 = tx * kOX - 1, y0 = ty * kOY - 1;  // global coordinates of column (0, 0)
   const int z0 = zc * A.zlen;
   const int z1 = min(z0 + A.zlen, A.nz);
@@ -144,6 +145,7 @@ __device__ __forceinline__ void filter_body(const FilterArgs& A, const WidthArgs
   const bool interior = (cx >= 1) && (cx <= kOX) && (cy >= 1) && (cy <= kOY) && (gx < A.nx) &&
                         (gy < A.ny);
   const bool stat_wave = (tid >> 6) < kStatWaves;
+  const bool need_grad = needs_gradient(W);
 
   T ring[5][D];
 #pragma unroll
@@ -258,7 +260,7 @@ __device__ __forceinline__ void filter_body(const FilterArgs& A, const WidthArgs
         }
       }
     }
-    if (k < 2 * R + 1) continue;  // gradient needs the plane above as well (uniform)
+    if (k < 2 * R + 1 || !need_grad) continue;  // the gradient needs the plane above (uniform)
     const int zg = zo - 1;
     if (zg < z0 || zg >= z1) continue;  // uniform
     __syncthreads();
@@ -294,14 +296,14 @@ __device__ __forceinline__ void filter_body(const FilterArgs& A, const WidthArgs
         for (int s = 0; s < 6; ++s) P.tgm[s] = P.tsm[s] = 0.f;
         P.ksgs = P.nut = P.omt = 0.f;
       }
-      if (stat_wave) {
+      if (stat_wave && W.partials) {
         StatIn I;
         stat_inputs(rb, u, tau, P, valid, I);
         stat_add(I, acc);
       }
     }
   }
-  if (stat_wave) {
+  if (stat_wave && W.partials) {
     write_stats(W.partials + ((int64_t)item * kStatWaves + (tid >> 6)) * kNStat, acc);
   }
 }

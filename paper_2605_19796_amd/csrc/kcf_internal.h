@@ -55,6 +55,7 @@ struct FilterArgs {
   int ntx, nty, ntiles;   // output tiles in x, y and their product
   int nzc, zlen;          // z chunks per column and their length
   int tiles_per_xcd;      // tiles of one XCD's contiguous band
+  int strip_w;            // tile numbering: strips of strip_w tiles, or plain rows when 0
   int nw;                 // widths in this launch
   WidthArgs wa[4];
 };
@@ -97,6 +98,7 @@ struct BoxGeom {
   int threads;         // threads per workgroup
   int stat_waves;      // per-wave statistics records per (tile, z-chunk) item
   int blocks_per_cu;   // resident workgroups per CU
+  int strip_w;         // tile numbering (FilterArgs::strip_w)
 };
 bool box_supported(int R, int fp64);
 BoxGeom box_geometry(int R, int fp64);

@@ -71,6 +71,8 @@ _SIGS = {
     "kcf_ctx_destroy": (None, [C.c_void_p]),
     "kcf_ctx_enable_timing": (C.c_int, [C.c_void_p, C.c_int]),
     "kcf_ctx_kernel_ms": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "kcf_ctx_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_float), C.c_int,
+                                       C.POINTER(C.c_int)]),
     "kcf_filter_taps": (C.c_int, [C.c_int, C.c_int, C.c_double, C.POINTER(C.c_float), C.c_int,
                                   C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "kcf_filter_favre": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.POINTER(Filter), C.c_int,
@@ -221,6 +223,13 @@ class Context:
         n = C.c_int()
         check(self._lib.kcf_ctx_kernel_ms(self.handle, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def kernel_times(self, cap=4096):
+        """Per-launch times (ms) of the timed launches since the last reset, in launch order."""
+        buf = (C.c_float * cap)()
+        n = C.c_int()
+        check(self._lib.kcf_ctx_kernel_times(self.handle, buf, cap, C.byref(n)))
+        return list(buf[:n.value])
 
     def filter_favre(self, rho, u, h, filters, outs, cp=None, stats=True):
         """rho (nz,ny,nx), u (3,nz,ny,nx) device float32; filters: list of (kind, n[, precision]);

@@ -135,8 +135,8 @@ def test_gauss8_full_field_64(ctx):
     check_stats(st[0], ora)
 
 
-def test_multiwidth_fused_matches_single_and_oracle(ctx):
-    say("[gpu] fused box widths 2,4,8,16 at 40^3")
+def test_multiwidth_call_matches_single_and_oracle(ctx):
+    say("[gpu] box widths 2,4,8,16 in one call at 40^3")
     rho, u = synth.workload_fields("c512_box_multi", n=40)
     rho, u = rho.numpy(), u.numpy()
     h = 2 * math.pi / 40
@@ -146,13 +146,31 @@ def test_multiwidth_fused_matches_single_and_oracle(ctx):
         ora = F.full_path(rho, u, kind, nd, h)
         check_fields(gpu[i], oracle_as_gpu_layout(ora))
         check_stats(st[i], ora)
-        # a single-width launch splits z into different chunks, so its FP32 running sums
-        # restart at different planes: both agree with the oracle, and with each other, to the
-        # parity tolerance
+        # every width of a multi-width call runs the same launch as a single-width call
         single, st1 = run_gpu(ctx, rho, u, h, [(kind, nd)])
         for f in ALL:
-            d = rel(gpu[i][f], single[0][f])
-            assert d <= TOL, (nd, f, d)
+            assert np.array_equal(gpu[i][f], single[0][f]), (nd, f)
+        assert st1[0]["raw"] == st[i]["raw"], nd
+
+
+@pytest.mark.parametrize("kind,nd", [(F.BOX, 2), (F.BOX, 16), (F.GAUSS, 4)])
+def test_fields_without_statistics(ctx, kind, nd):
+    """With statistics off and only the Favre fields requested the gradient epilogue is
+    skipped; the fields are those of the full call, bit for bit."""
+    say(f"[gpu] Favre fields without statistics kind={kind} n={nd}")
+    rho, u = synth.workload_fields("c512_box_multi", n=36)
+    rho, u = rho.numpy(), u.numpy()
+    h = 2 * math.pi / 36
+    full, _ = run_gpu(ctx, rho, u, h, [(kind, nd)])
+    r, uu = dev(rho), dev(u)
+    fields = ("rho_bar", "ut", "tau")
+    outs = [kcf.alloc_outputs(rho.shape, "cuda", fields)]
+    for t in outs[0].values():
+        t.fill_(float("nan"))
+    assert ctx.filter_favre(r, uu, h, [(kind, nd)], outs, stats=False) is None
+    torch.cuda.synchronize()
+    for f in fields:
+        assert np.array_equal(outs[0][f].cpu().numpy(), full[0][f]), f
 
 
 @pytest.mark.parametrize("cp", [dict(gm_form=1), dict(m2_mode=1), dict(ksgs_rho_ref=1),
