@@ -477,13 +477,13 @@ int kcf_input_stats(kcf_ctx* c, const kcf_grid* grid, const float* rho, const fl
   S.nz = grid->nz;
   S.ntot = (int64_t)grid->nx * grid->ny * grid->nz;
   S.inv60h = 1.0 / (60.0 * grid->h);
-  int64_t nb = (S.ntot + 255) / 256;
-  if (nb > 4096) nb = 4096;
-  if ((rc = ensure_partials(c, (size_t)nb * 4 * 4))) return rc;
+  if (grid->ny > 65535) return fail(KCF_EUNSUPPORTED, "ny above 65535");
+  const int64_t nrec = input_stats_records(S);
+  if ((rc = ensure_partials(c, (size_t)nrec * 4))) return rc;
   S.partials = c->d_part;
-  hipError_t e = launch_input_stats(S, (int)nb, c->stream);
+  hipError_t e = launch_input_stats(S, c->stream);
   if (e != hipSuccess) return hip_fail(e, "input stats launch");
-  e = launch_reduce(c->d_part, (int)nb * 4, 4, c->d_sums, c->stream);
+  e = launch_reduce(c->d_part, (int)nrec, 4, c->d_sums, c->stream);
   if (e != hipSuccess) return hip_fail(e, "reduce launch");
   KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * 4, hipMemcpyDeviceToHost,
                          c->stream), "stats copy");

@@ -44,7 +44,6 @@ struct Lds {
   static constexpr int doubles = (bytes + 7) / 8;
 };
 
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
 
 // ---------------------------------------------------------------- z ring (compile-time slots)
 template <int D, int S, typename T, typename WT>
@@ -316,24 +315,6 @@ __global__ void __launch_bounds__(kNT) k_filter1(FilterArgs A) {
   filter_body<R, T>(A, A.wa[widx], item, reinterpret_cast<unsigned char*>(smem));
 }
 
-constexpr int cmax4(int a, int b, int c, int d) { return cmax(cmax(a, b), cmax(c, d)); }
-
-// Four box widths 2h, 4h, 8h, 16h (radii 1, 2, 4, 8) in one launch: the two narrow widths
-// accumulate in FP64, the two wide ones in FP32.
-__global__ void __launch_bounds__(kNT) k_filter_box4(FilterArgs A) {
-  __shared__ double smem[cmax4(Lds<1, double>::doubles, Lds<2, double>::doubles,
-                               Lds<4, float>::doubles, Lds<8, float>::doubles)];
-  int widx, item;
-  if (!map_block(A, widx, item)) return;
-  unsigned char* s = reinterpret_cast<unsigned char*>(smem);
-  switch (widx) {
-    case 0: filter_body<1, double>(A, A.wa[0], item, s); break;
-    case 1: filter_body<2, double>(A, A.wa[1], item, s); break;
-    case 2: filter_body<4, float>(A, A.wa[2], item, s); break;
-    default: filter_body<8, float>(A, A.wa[3], item, s); break;
-  }
-}
-
 // ---------------------------------------------------------------- standalone closure pass
 constexpr int kCT = 256;
 
@@ -397,49 +378,82 @@ __global__ void __launch_bounds__(kCT) k_grad_closure(ClosureArgs C) {
 }
 
 // ---------------------------------------------------------------- input statistics
-__device__ __forceinline__ double d6(const float* f, int64_t c, int64_t sp1, int64_t sp2,
-                                     int64_t sp3, int64_t sm1, int64_t sm2, int64_t sm3) {
-  return 45.0 * ((double)f[sp1] - (double)f[sm1]) - 9.0 * ((double)f[sp2] - (double)f[sm2]) +
-         ((double)f[sp3] - (double)f[sm3]);
+// E_k, enstrophy (sixth-order central vorticity) and <rho> of the unfiltered input. A block
+// owns kIX consecutive points of one x-row and kIZ planes; each thread marches along z with
+// the seven planes of u_x and u_y that the z-derivatives need held in registers, and reads
+// the x and y neighbours of its plane through the caches.
+constexpr int kIX = 128, kIZ = 16;
+
+__device__ __forceinline__ double d6(float p1, float p2, float p3, float m1, float m2, float m3) {
+  return 45.0 * ((double)p1 - (double)m1) - 9.0 * ((double)p2 - (double)m2) +
+         ((double)p3 - (double)m3);
 }
 
-__global__ void __launch_bounds__(kCT) k_input_stats(InputStatArgs S) {
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+__global__ void __launch_bounds__(kIX) k_input_stats(InputStatArgs S) {
+  const int x = blockIdx.x * kIX + threadIdx.x;
+  const int y = blockIdx.y;
+  const int z0 = blockIdx.z * kIZ;
+  const int z1 = min(z0 + kIZ, S.nz);
+  const bool valid = x < S.nx;
+  const int xc = valid ? x : 0;
   const int64_t plane = (int64_t)S.nx * S.ny;
-  const int64_t stride = (int64_t)gridDim.x * kCT;
-  for (int64_t g = (int64_t)blockIdx.x * kCT + threadIdx.x; g < S.ntot; g += stride) {
-    const int x = (int)(g % S.nx);
-    const int y = (int)((g / S.nx) % S.ny);
-    const int z = (int)(g / plane);
-    int64_t ox[6], oy[6], oz[6];  // +1 +2 +3 -1 -2 -3
+  const int64_t row = (int64_t)y * S.nx;
+  const float* ux = S.u;
+  const float* uy = S.u + S.ntot;
+  const float* uz = S.u + 2 * S.ntot;
+  int xo[6];      // x + 1, x + 2, x + 3, x - 1, x - 2, x - 3 (periodic)
+  int64_t yo[6];  // the same rows, as offsets
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      ox[m] = g - x + wrapi(x + m + 1, S.nx);
-      ox[m + 3] = g - x + wrapi(x - m - 1, S.nx);
-      oy[m] = g + (int64_t)(wrapi(y + m + 1, S.ny) - y) * S.nx;
-      oy[m + 3] = g + (int64_t)(wrapi(y - m - 1, S.ny) - y) * S.nx;
-      oz[m] = g + (int64_t)(wrapi(z + m + 1, S.nz) - z) * plane;
-      oz[m + 3] = g + (int64_t)(wrapi(z - m - 1, S.nz) - z) * plane;
-    }
-    const float* ux = S.u;
-    const float* uy = S.u + S.ntot;
-    const float* uz = S.u + 2 * S.ntot;
-    const double wx = (d6(uz, g, oy[0], oy[1], oy[2], oy[3], oy[4], oy[5]) -
-                       d6(uy, g, oz[0], oz[1], oz[2], oz[3], oz[4], oz[5])) * S.inv60h;
-    const double wy = (d6(ux, g, oz[0], oz[1], oz[2], oz[3], oz[4], oz[5]) -
-                       d6(uz, g, ox[0], ox[1], ox[2], ox[3], ox[4], ox[5])) * S.inv60h;
-    const double wz = (d6(uy, g, ox[0], ox[1], ox[2], ox[3], ox[4], ox[5]) -
-                       d6(ux, g, oy[0], oy[1], oy[2], oy[3], oy[4], oy[5])) * S.inv60h;
+  for (int m = 0; m < 3; ++m) {
+    xo[m] = wrapi(xc + m + 1, S.nx);
+    xo[m + 3] = wrapi(xc - m - 1, S.nx);
+    yo[m] = (int64_t)wrapi(y + m + 1, S.ny) * S.nx;
+    yo[m + 3] = (int64_t)wrapi(y - m - 1, S.ny) * S.nx;
+  }
+  float wx[7], wy[7];  // u_x, u_y at planes z - 3 .. z + 3
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    const int64_t g = (int64_t)wrapi(z0 - 3 + m, S.nz) * plane + row + xc;
+    wx[m] = ux[g];
+    wy[m] = uy[g];
+  }
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (int z = z0; z < z1; ++z) {
+    const int64_t gp = (int64_t)wrapi(z + 3, S.nz) * plane + row + xc;
+    wx[6] = ux[gp];
+    wy[6] = uy[gp];
+    const int64_t base = (int64_t)z * plane;
+    const int64_t g = base + row + xc;
+    const float* pyy = uy + base + row;
+    const float* pzx = uz + base + row;
+    const float* pxb = ux + base + xc;
+    const float* pzb = uz + base + xc;
+    const double dy_uz = d6(pzb[yo[0]], pzb[yo[1]], pzb[yo[2]], pzb[yo[3]], pzb[yo[4]], pzb[yo[5]]);
+    const double dy_ux = d6(pxb[yo[0]], pxb[yo[1]], pxb[yo[2]], pxb[yo[3]], pxb[yo[4]], pxb[yo[5]]);
+    const double dx_uz = d6(pzx[xo[0]], pzx[xo[1]], pzx[xo[2]], pzx[xo[3]], pzx[xo[4]], pzx[xo[5]]);
+    const double dx_uy = d6(pyy[xo[0]], pyy[xo[1]], pyy[xo[2]], pyy[xo[3]], pyy[xo[4]], pyy[xo[5]]);
+    const double dz_uy = d6(wy[4], wy[5], wy[6], wy[2], wy[1], wy[0]);
+    const double dz_ux = d6(wx[4], wx[5], wx[6], wx[2], wx[1], wx[0]);
+    const double ox = (dy_uz - dz_uy) * S.inv60h;
+    const double oy = (dz_ux - dx_uz) * S.inv60h;
+    const double oz = (dx_uy - dy_ux) * S.inv60h;
     const double r = S.rho[g];
-    const double vx = ux[g], vy = uy[g], vz = uz[g];
+    const double vx = wx[3], vy = wy[3], vz = uz[g];
     const double ek = 0.5 * r * (vx * vx + vy * vy + vz * vz);
-    const double en = 0.5 * (wx * wx + wy * wy + wz * wz);
-    if (isfinite(ek) && isfinite(en) && isfinite(r)) {
-      a0 += r;
-      a1 += ek;
-      a2 += en;
-    } else {
-      a3 += 1.0;
+    const double en = 0.5 * (ox * ox + oy * oy + oz * oz);
+    if (valid) {
+      if (isfinite(ek + en + r)) {
+        a0 += r;
+        a1 += ek;
+        a2 += en;
+      } else {
+        a3 += 1.0;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      wx[m] = wx[m + 1];
+      wy[m] = wy[m + 1];
     }
   }
   // fixed-order wave reduction, then one partial per wave
@@ -451,7 +465,8 @@ __global__ void __launch_bounds__(kCT) k_input_stats(InputStatArgs S) {
     a3 += __shfl_xor(a3, d);
   }
   if (__lane_id() == 0) {
-    double* p = S.partials + ((int64_t)blockIdx.x * (kCT / 64) + (threadIdx.x >> 6)) * 4;
+    const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    double* p = S.partials + (blk * (kIX / 64) + (threadIdx.x >> 6)) * 4;
     p[0] = a0;
     p[1] = a1;
     p[2] = a2;
@@ -515,13 +530,6 @@ hipError_t launch_filter(const FilterArgs& a, const int* radii, const int* fp64,
                          hipStream_t s) {
   const dim3 block(kNT);
   const dim3 grid(nblocks);
-  if (a.nw == 4) {
-    if (!(radii[0] == 1 && radii[1] == 2 && radii[2] == 4 && radii[3] == 8 && fp64[0] &&
-          fp64[1] && !fp64[2] && !fp64[3]))
-      return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_filter_box4, grid, block, 0, s, a);
-    return hipGetLastError();
-  }
   if (a.nw != 1) return hipErrorInvalidValue;
 #define KCF_CASE(RR)                                                              \
   case RR:                                                                        \
@@ -557,8 +565,13 @@ hipError_t launch_grad_closure(const ClosureArgs& a, int* nblocks, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_input_stats(const InputStatArgs& a, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_input_stats, dim3(nblocks), dim3(kCT), 0, s, a);
+int64_t input_stats_records(const InputStatArgs& a) {
+  return (int64_t)((a.nx + kIX - 1) / kIX) * a.ny * ((a.nz + kIZ - 1) / kIZ) * (kIX / 64);
+}
+
+hipError_t launch_input_stats(const InputStatArgs& a, hipStream_t s) {
+  const dim3 grid((a.nx + kIX - 1) / kIX, a.ny, (a.nz + kIZ - 1) / kIZ);
+  hipLaunchKernelGGL(k_input_stats, grid, dim3(kIX), 0, s, a);
   return hipGetLastError();
 }
 

@@ -76,7 +76,7 @@ struct InputStatArgs {
   int nx, ny, nz;
   int64_t ntot;
   double inv60h;
-  double* partials;       // [blocks][4]
+  double* partials;       // [records][4]
 };
 
 // launchers (kcf_filter.hip)
@@ -85,7 +85,8 @@ hipError_t launch_filter(const FilterArgs& a, const int* radii, const int* fp64,
 bool fp64_supported(int kernel_radius);
 hipError_t launch_grad_closure(const ClosureArgs& a, int* nblocks, hipStream_t s);
 int grad_closure_blocks(int64_t ntot);
-hipError_t launch_input_stats(const InputStatArgs& a, int nblocks, hipStream_t s);
+int64_t input_stats_records(const InputStatArgs& a);  // per-wave partial records
+hipError_t launch_input_stats(const InputStatArgs& a, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nparts, int nstat, double* out,
                          hipStream_t s);
 hipError_t launch_reduce_check(const float* a, const float* b, int64_t n, double* partials,
