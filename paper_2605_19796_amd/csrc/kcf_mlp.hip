@@ -632,13 +632,29 @@ __global__ void __launch_bounds__(256) k_colstats(const float* __restrict__ X, i
 }
 
 // ---------------------------------------------------------------- inference over a field
-// One wave per 16 consecutive points along x. The gradient model
-// tau_gm = rho_bar C2 G G^T replaces the network where the standardised inputs leave the
-// training box or are not finite.
+// Makes LDS writes of this wave visible to its other lanes (LDS only: outstanding global
+// memory operations are not waited for).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int kXS = 17;  // LDS row stride of one point's 16 standardised inputs (odd: no conflicts)
+constexpr int kYS = 9;   // LDS row stride of one point's outputs
+
+// One wave per 64 consecutive points. Every lane derives the gradient, the 14 inputs and the
+// envelope test of its own point; the standardised inputs go through LDS into the MFMA
+// layout of four 16-point tiles, and the network outputs come back through LDS to the lane of
+// their point, which applies the unstandardisation, or the gradient model
+// tau_gm = rho_bar C2 G G^T where the inputs leave the training box or are not finite, and
+// stores tau (64 consecutive points per store).
 __global__ void __launch_bounds__(256) k_infer(MlpArgs M, InferArgs I) {
   __shared__ __attribute__((aligned(16))) __bf16 sW[kPF3 + 1024];
   __shared__ float sB[208];
   __shared__ float sNorm[68];
+  __shared__ float sX[4 * 64 * kXS];
+  __shared__ float sY[4 * 64 * kYS];
   stage_params(M, sW, sB, kPF3 + 1024);
   if (threadIdx.x < 14) {
     sNorm[threadIdx.x] = M.x_mu[threadIdx.x];
@@ -653,54 +669,86 @@ __global__ void __launch_bounds__(256) k_infer(MlpArgs M, InferArgs I) {
   __syncthreads();
   const int lane = __lane_id();
   const int g = lane >> 4, p = lane & 15;
-  const int64_t plane = (int64_t)I.nx * I.ny;
+  const int wv = threadIdx.x >> 6;
+  float* xw = sX + wv * 64 * kXS;
+  float* yw = sY + wv * 64 * kYS;
   const int64_t ntiles = (I.ntot + 15) / 16;
+  const int64_t nchunks = (I.ntot + 63) / 64;
   int64_t fallback = 0;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles;
-       tile += (int64_t)gridDim.x * 4) {
-    const int64_t gi = tile * 16 + p;
+  for (int64_t chunk = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv); chunk < nchunks;
+       chunk += (int64_t)gridDim.x * 4) {
+    // coordinates of the chunk's first point (uniform), then of this lane's point
+    const int64_t base = chunk * 64;
+    const int64_t row = base / I.nx;
+    int x = (int)(base - row * I.nx) + lane;
+    int y = (int)(row % I.ny), z = (int)(row / I.ny);
+    while (x >= I.nx) {
+      x -= I.nx;
+      if (++y == I.ny) {
+        y = 0;
+        ++z;
+      }
+    }
+    const int64_t gi = base + lane;
     const bool inside = gi < I.ntot;
+    if (!inside) {
+      x = I.nx - 1;
+      y = I.ny - 1;
+      z = I.nz - 1;
+    }
     const int64_t gc = inside ? gi : I.ntot - 1;
-    const int x = (int)(gc % I.nx), y = (int)((gc / I.nx) % I.ny), z = (int)(gc / plane);
     float G[3][3];
     grad_at(I.ut, gc, x, y, z, I.nx, I.ny, I.nz, I.ntot, I.inv2h, G);
     float f[14];
     features14(G, I.delta, f);
-    // standardised inputs of this lane and the envelope test of all 14
     bool out = false;
-    float xs[4] = {0.f, 0.f, 0.f, 0.f};
+    float* xr = xw + lane * kXS;
 #pragma unroll
     for (int k = 0; k < 14; ++k) {
       const float v = (f[k] - sNorm[k]) * sNorm[14 + k];
       out = out || !(v >= sNorm[40 + k] && v <= sNorm[54 + k]);
-      if (k >> 2 == g) xs[k & 3] = isfinite(v) ? v : 0.f;
+      xr[k] = isfinite(v) ? v : 0.f;
     }
-    Fwd F;
-    forward(sW, sB, pack4(xs[0], xs[1], xs[2], xs[3]), F);
+    xr[14] = 0.f;
+    xr[15] = 0.f;
+    wave_lds_sync();
+#pragma unroll 1
+    for (int t = 0; t < 4; ++t) {
+      const float* src = xw + (16 * t + p) * kXS + 4 * g;
+      Fwd F;
+      forward(sW, sB, pack4(src[0], src[1], src[2], src[3]), F);
+      float* dst = yw + (16 * t + p) * kYS + 4 * g;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (4 * g + i < 6) dst[i] = F.y[i];
+    }
+    wave_lds_sync();
+    const float* yr = yw + lane * kYS;
     const float rb = I.rho_bar[gc];
-    // gradient-model fallback (Taylor form, coefficient C2)
     const int ii[6] = {0, 0, 0, 1, 1, 2};
     const int jj[6] = {0, 1, 2, 1, 2, 2};
+    if (inside) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int c = 4 * g + i;
-      if (c < 6 && inside) {
+      for (int c = 0; c < 6; ++c) {
         float v;
         if (out) {
           const int a = ii[c], bb = jj[c];
           v = I.gm_coef * rb * (G[a][0] * G[bb][0] + G[a][1] * G[bb][1] + G[a][2] * G[bb][2]);
         } else {
-          v = rb * fmaf(sNorm[34 + c], F.y[i], sNorm[28 + c]);
+          v = rb * fmaf(sNorm[34 + c], yr[c], sNorm[28 + c]);
         }
         I.tau[c * I.ntot + gi] = v;
       }
     }
-    const unsigned long long bal = __ballot(out && inside && g == 0);
-    if (I.mask && lane == 0) I.mask[tile] = (uint16_t)(bal & 0xFFFFull);
-    if (lane == 0) fallback += __popcll(bal & 0xFFFFull);
+    const unsigned long long bal = __ballot(out && inside);
+    if (I.mask && lane < 4 && chunk * 4 + lane < ntiles)
+      I.mask[chunk * 4 + lane] = (uint16_t)((bal >> (16 * lane)) & 0xFFFFull);
+    fallback += __popcll(bal);
+    // the outputs of this chunk are read before the next chunk overwrites them
+    wave_lds_sync();
   }
   if (I.fallback_part && lane == 0)
-    I.fallback_part[(int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)] = fallback;
+    I.fallback_part[(int64_t)blockIdx.x * 4 + wv] = fallback;
 }
 
 }  // namespace

@@ -403,8 +403,8 @@ int kcf_mlp_infer_field(kcf_mlp* m, const kcf_grid* grid, const float* rho_bar, 
   I.gm_coef = (float)m2;
   I.tau = tau;
   I.mask = mask;
-  const int64_t tiles = (I.ntot + 15) / 16;
-  int blocks = (int)std::min<int64_t>(4096, (tiles + 3) / 4);
+  const int64_t chunks = (I.ntot + 63) / 64;  // one wave per 64 points, four waves a block
+  int blocks = (int)std::min<int64_t>(4096, (chunks + 3) / 4);
   I.fallback_part = nullptr;
   if (n_fallback) {
     if (m->fb_cap < blocks * 4) {
