@@ -62,7 +62,7 @@ typedef struct { int nx, ny, nz; double h; } kcf_grid;
 /* kind: KCF_BOX (delta_over_h even, >= 2) or KCF_GAUSS (delta_over_h >= 1).
  * precision of the filter sums and of the Favre/tau assembly: 0 = auto (FP64 for widths up
  * to 4h, where tau is a small difference of large filtered products, FP32 above), 1 = FP32,
- * 2 = FP64 (radii up to 8). Outputs are float32 in every case. */
+ * 2 = FP64. Outputs are float32 in every case. */
 typedef struct { int kind; int delta_over_h; int precision; } kcf_filter;
 
 /* Device output buffers of one filter width; any pointer may be NULL (not produced). */
@@ -150,9 +150,14 @@ int kcf_filter_taps(int kind, int delta_over_h, double h, float *w, int cap, int
  * are evaluated on chip, and the call synchronises the stream. Without stats the gradient
  * and closures are evaluated only for the fields outs[f] asks for (none for rho_bar, ut and
  * tau alone).
+ * Box widths up to 16h (FP32) or 8h (FP64) run as one fused kernel per width. Other widths
+ * (Gaussian, wider box) run as an x-y pass into a context buffer of at most 8 GiB of
+ * filtered products (the whole field or z slabs), a z pass writing rho_bar, ut, tau, and,
+ * when the gradient is needed, the pass of kcf_grad_closure on those fields; if the caller
+ * does not ask for rho_bar, ut or tau the context holds them in a scratch of 10 N floats.
  * Errors: KCF_EINVAL for null rho/u/outs/grid, n < 3 in any direction, n_filters outside
- * 1..4, bad filter kind or width; KCF_EUNSUPPORTED when 2R+1 exceeds a grid dimension or
- * R > 12. */
+ * 1..4, bad filter kind or width; KCF_EUNSUPPORTED when 2R+1 exceeds a grid dimension,
+ * R > 12 or ny > 65535; KCF_ENOMEM when a context buffer cannot be allocated. */
 int kcf_filter_favre(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filters,
                      int n_filters, const float *rho, const float *u, const kcf_outputs *outs,
                      const kcf_closure_params *cp, kcf_width_stats *stats);

@@ -19,6 +19,10 @@ struct kcf_ctx {
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
   size_t ev_used = 0;
+  void* d_xy = nullptr;        // slab buffer of the general-tap filter
+  size_t xy_cap = 0;           // bytes
+  float* d_fld = nullptr;      // Favre fields the caller did not ask for (10 N floats)
+  size_t fld_cap = 0;          // floats
 };
 
 namespace {
@@ -53,6 +57,21 @@ int ensure_partials(kcf_ctx* c, size_t n) {
   if (hipMalloc(&c->d_part, n * sizeof(double)) != hipSuccess)
     return fail(KCF_ENOMEM, "cannot allocate FP64 partial sums");
   c->part_cap = n;
+  return KCF_OK;
+}
+
+// Device buffers that only grow; the stream is drained before one is replaced.
+template <typename P>
+int ensure_buffer(kcf_ctx* c, P*& ptr, size_t& cap, size_t bytes, const char* what) {
+  if (bytes <= cap) return KCF_OK;
+  if (ptr) {
+    hipStreamSynchronize(c->stream);
+    hipFree(ptr);
+    ptr = nullptr;
+    cap = 0;
+  }
+  if (hipMalloc((void**)&ptr, bytes) != hipSuccess) return fail(KCF_ENOMEM, what);
+  cap = bytes;
   return KCF_OK;
 }
 
@@ -257,6 +276,8 @@ void kcf_ctx_destroy(kcf_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
   if (c->d_part) hipFree(c->d_part);
+  if (c->d_xy) hipFree(c->d_xy);
+  if (c->d_fld) hipFree(c->d_fld);
   if (c->d_sums) hipFree(c->d_sums);
   if (c->h_sums) hipHostFree(c->h_sums);
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
@@ -319,7 +340,7 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
   if (nf < 1 || nf > 4) return fail(KCF_EINVAL, "n_filters must be 1..4");
   if ((rc = check_closure(cp))) return rc;
   Taps taps[4];
-  int radii[4], kr[4], fp64[4];
+  int radii[4], fp64[4];
   for (int f = 0; f < nf; ++f) {
     if ((rc = compute_taps(filters[f].kind, filters[f].delta_over_h, grid->h, taps[f]))) return rc;
     radii[f] = taps[f].R;
@@ -327,23 +348,21 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     const int nmin = std::min(grid->nx, std::min(grid->ny, grid->nz));
     if (2 * taps[f].R + 1 > nmin)
       return fail(KCF_EUNSUPPORTED, "filter support 2R+1 exceeds the grid");
-    kr[f] = kernel_radius_for(taps[f].R);
     const int p = filters[f].precision;
     if (p < 0 || p > 2) return fail(KCF_EINVAL, "precision must be 0 (auto), 1 (fp32) or 2 (fp64)");
     fp64[f] = p == 2 || (p == 0 && filters[f].delta_over_h <= 4);
-    if (fp64[f] && !fp64_supported(kr[f]))
-      return fail(KCF_EUNSUPPORTED, "FP64 accumulation is limited to radii <= 8");
   }
+  if (grid->ny > 65535) return fail(KCF_EUNSUPPORTED, "ny above 65535");
   KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
-  // kernel per width: the sliding-sum box kernel where it applies, the general one otherwise
+  // kernel per width: the sliding-sum box kernel where it applies, the general-tap filter
+  // followed by the gradient/closure pass otherwise
   int use_box[4];
   for (int f = 0; f < nf; ++f)
     use_box[f] = filters[f].kind == KCF_BOX && box_supported(radii[f], fp64[f]);
   const int64_t ntot = (int64_t)grid->nx * grid->ny * grid->nz;
-  auto geometry = [&](FilterArgs& A, int f) {
-    const bool box = use_box[f] != 0;
-    const BoxGeom bg = box ? box_geometry(radii[f], fp64[f]) : BoxGeom{};
-    const int rr = box ? radii[f] : kr[f];
+  const int64_t plane = (int64_t)grid->nx * grid->ny;
+  auto box_args = [&](FilterArgs& A, int f) {
+    const BoxGeom bg = box_geometry(radii[f], fp64[f]);
     std::memset(&A, 0, sizeof(A));
     A.rho = rho;
     A.u = u;
@@ -352,54 +371,131 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     A.nz = grid->nz;
     A.ntot = ntot;
     A.inv2h = (float)(1.0 / (2.0 * grid->h));
-    const int ox = box ? bg.tile_x : kOX, oy = box ? bg.tile_y : kOY;
-    A.ntx = (grid->nx + ox - 1) / ox;
-    A.nty = (grid->ny + oy - 1) / oy;
+    A.ntx = (grid->nx + bg.tile_x - 1) / bg.tile_x;
+    A.nty = (grid->ny + bg.tile_y - 1) / bg.tile_y;
     A.ntiles = A.ntx * A.nty;
-    A.nzc = choose_zchunks(A.ntiles, grid->nz, rr, box ? bg.blocks_per_cu : 1);
+    A.nzc = choose_zchunks(A.ntiles, grid->nz, radii[f], bg.blocks_per_cu);
     A.zlen = (grid->nz + A.nzc - 1) / A.nzc;
     A.nzc = (grid->nz + A.zlen - 1) / A.zlen;
     A.tiles_per_xcd = (A.ntiles * A.nzc + 7) / 8;
-    A.strip_w = box ? bg.strip_w : 0;
-    A.nw = 1;
+    A.strip_w = bg.strip_w;
   };
-  // partial sums: [width][items][waves][kNStat]
-  size_t part_width[4], part_off[4];
+  ClosureArgs CG;  // geometry of the gradient/closure pass (same for every width)
+  std::memset(&CG, 0, sizeof(CG));
+  CG.nx = grid->nx;
+  CG.ny = grid->ny;
+  CG.nz = grid->nz;
+  CG.ntot = ntot;
+  CG.inv2h = (float)(1.0 / (2.0 * grid->h));
+  // partial sums: [width][records][kNStat]
+  size_t part_off[4];
   int nparts[4];
   {
     size_t off = 0;
     for (int f = 0; f < nf; ++f) {
-      FilterArgs G;
-      geometry(G, f);
-      const int waves = use_box[f] ? box_geometry(radii[f], fp64[f]).stat_waves : kStatWaves;
-      nparts[f] = G.ntiles * G.nzc * waves;
-      part_width[f] = (size_t)nparts[f] * kNStat;
+      if (use_box[f]) {
+        FilterArgs G;
+        box_args(G, f);
+        nparts[f] = G.ntiles * G.nzc * box_geometry(radii[f], fp64[f]).stat_waves;
+      } else {
+        nparts[f] = (int)grad_closure_records(CG);
+      }
       part_off[f] = off;
-      off += part_width[f];
+      off += (size_t)nparts[f] * kNStat;
     }
     if (stats && (rc = ensure_partials(c, off))) return rc;
   }
-  auto fill_width = [&](WidthArgs& W, int f, int K) {
+  auto fill_width = [&](WidthArgs& W, int f) {
     std::memset(&W, 0, sizeof(W));
-    const int R = taps[f].R;
-    for (int m = 0; m < 2 * K + 1; ++m) {
-      const int mm = m - (K - R);
-      W.wd[m] = (mm >= 0 && mm < 2 * R + 1) ? taps[f].wd[mm] : 0.0;
-      W.w[m] = (float)W.wd[m];
-    }
     set_outputs(W, &outs[f]);
     set_closure(W, cp, filters[f].delta_over_h * grid->h, taps[f].m2);
     W.partials = stats ? c->d_part + part_off[f] : nullptr;
   };
   for (int f = 0; f < nf; ++f) {
-    FilterArgs A;
-    const bool box = use_box[f] != 0;
-    geometry(A, f);
-    fill_width(A.wa[0], f, box ? radii[f] : kr[f]);
+    if (use_box[f]) {
+      FilterArgs A;
+      box_args(A, f);
+      fill_width(A.wa, f);
+      if ((rc = timed_begin(c))) return rc;
+      hipError_t e = launch_box(A, radii[f], fp64[f], 8 * A.tiles_per_xcd, c->stream);
+      if (e != hipSuccess) return hip_fail(e, "box filter launch");
+      if ((rc = timed_end(c))) return rc;
+      continue;
+    }
+    // general taps: x-y pass into a z-slab buffer, z pass with Favre division, then the
+    // gradient/closure pass on the stored fields when anything needs the gradient
+    WidthArgs W;
+    fill_width(W, f);
+    const bool grad_pass = stats || W.grad || W.tau_gm || W.tau_smag || W.k_sgs || W.nu_t ||
+                           W.omega_t;
+    float* fb = W.rho_bar;
+    float* fu = W.ut;
+    float* ft = W.tau;
+    if (grad_pass && (!fb || !fu || !ft)) {
+      if ((rc = ensure_buffer(c, c->d_fld, c->fld_cap, sizeof(float) * 10 * (size_t)ntot,
+                              "cannot allocate Favre field scratch")))
+        return rc;
+      if (!fb) fb = c->d_fld;
+      if (!fu) fu = c->d_fld + ntot;
+      if (!ft) ft = c->d_fld + 4 * ntot;
+    }
+    TapArgs T;
+    std::memset(&T, 0, sizeof(T));
+    T.rho = rho;
+    T.u = u;
+    T.nx = grid->nx;
+    T.ny = grid->ny;
+    T.nz = grid->nz;
+    T.ntot = ntot;
+    T.ntx = (grid->nx + taps_tile_x() - 1) / taps_tile_x();
+    T.nty = (grid->ny + taps_tile_y() - 1) / taps_tile_y();
+    const int R = radii[f];
+    for (int m = 0; m < 2 * R + 1; ++m) {
+      T.wd[m] = taps[f].wd[m];
+      T.w[m] = (float)taps[f].wd[m];
+    }
+    T.rho_bar = fb;
+    T.ut = fu;
+    T.tau = ft;
+    // slab of planes whose x-y filtered products fit the buffer cap (the whole field if it can)
+    const size_t esize = fp64[f] ? sizeof(double) : sizeof(float);
+    const size_t per_plane = 10 * (size_t)plane * esize;
+    const int zt = taps_z_planes(fp64[f]);
+    int slab = grid->nz;
+    if (per_plane * (size_t)grid->nz > kTapBufferCap) {
+      slab = (int)(kTapBufferCap / per_plane) - 2 * R;
+      slab = std::max(zt, slab / zt * zt);
+      if (slab + 2 * R >= grid->nz) slab = grid->nz;
+    }
+    const int nbuf_max = slab == grid->nz ? grid->nz : slab + 2 * R;
+    if ((rc = ensure_buffer(c, c->d_xy, c->xy_cap, per_plane * (size_t)nbuf_max,
+                            "cannot allocate the filter slab buffer")))
+      return rc;
+    T.xy = c->d_xy;
     if ((rc = timed_begin(c))) return rc;
-    hipError_t e = box ? launch_box(A, radii[f], fp64[f], 8 * A.tiles_per_xcd, c->stream)
-                       : launch_filter(A, &kr[f], &fp64[f], 8 * A.tiles_per_xcd, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "filter launch");
+    for (int z0 = 0; z0 < grid->nz; z0 += slab) {
+      const int z1 = std::min(z0 + slab, grid->nz);
+      T.zo0 = z0;
+      T.zo1 = z1;
+      if (slab == grid->nz) {
+        T.zb = 0;
+        T.nbuf = grid->nz;
+      } else {
+        T.zb = z0 - R;
+        T.nbuf = (z1 - z0) + 2 * R;
+      }
+      hipError_t e = launch_taps(T, R, fp64[f], c->stream);
+      if (e != hipSuccess) return hip_fail(e, "general-tap filter launch");
+    }
+    if (grad_pass) {
+      ClosureArgs C = CG;
+      C.rho_bar = fb;
+      C.ut = fu;
+      C.tau = ft;
+      C.wa = W;
+      hipError_t e = launch_grad_closure(C, c->stream);
+      if (e != hipSuccess) return hip_fail(e, "closure launch");
+    }
     if ((rc = timed_end(c))) return rc;
   }
   if (stats) {
@@ -442,16 +538,16 @@ int kcf_grad_closure(kcf_ctx* c, const kcf_grid* grid, const float* rho_bar, con
   C.inv2h = (float)(1.0 / (2.0 * grid->h));
   set_outputs(C.wa, outs);
   set_closure(C.wa, cp, delta, m2);
-  const int nb = grad_closure_blocks(C.ntot);
+  if (grid->ny > 65535) return fail(KCF_EUNSUPPORTED, "ny above 65535");
+  const int64_t nrec = grad_closure_records(C);
   if (stats) {
-    if ((rc = ensure_partials(c, (size_t)nb * 4 * kNStat))) return rc;
+    if ((rc = ensure_partials(c, (size_t)nrec * kNStat))) return rc;
     C.wa.partials = c->d_part;
   }
-  int nb2 = 0;
-  hipError_t e = launch_grad_closure(C, &nb2, c->stream);
+  hipError_t e = launch_grad_closure(C, c->stream);
   if (e != hipSuccess) return hip_fail(e, "closure launch");
   if (stats) {
-    if ((rc = reduce_to_host(c, nb * 4, kNStat, 0))) return rc;
+    if ((rc = reduce_to_host(c, (int)nrec, kNStat, 0))) return rc;
     KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * kNStat, hipMemcpyDeviceToHost,
                            c->stream), "stats copy");
     KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");

@@ -338,9 +338,9 @@ __global__ void __launch_bounds__(TileFor<R>::BT)
     __attribute__((amdgpu_waves_per_eu(TileFor<R>::WAVES, TileFor<R>::WAVES)))
     k_box1(FilterArgs A) {
   __shared__ double smem[BoxLds<R, T>::doubles];
-  int widx, item;
-  if (!map_block(A, widx, item)) return;
-  box_body<R, T>(A, A.wa[widx], item, reinterpret_cast<unsigned char*>(smem));
+  int item;
+  if (!map_block(A, item)) return;
+  box_body<R, T>(A, A.wa, item, reinterpret_cast<unsigned char*>(smem));
 }
 
 template <int R, typename T>
@@ -391,7 +391,6 @@ BoxGeom box_geometry(int R, int fp64) {
 }
 
 hipError_t launch_box(const FilterArgs& a, int R, int fp64, int nblocks, hipStream_t s) {
-  if (a.nw != 1) return hipErrorInvalidValue;
   hipError_t e = hipErrorInvalidValue;
   dispatch(R, fp64, [&]<int RR, typename T>() { e = launch_of<RR, T>(a, nblocks, s); });
   return e;

@@ -281,15 +281,12 @@ __device__ __forceinline__ void tile_coords(const FilterArgs& A, int t, int& tx,
 }
 
 // XCD-aware block mapping: consecutive block ids go to different XCDs, so block L is
-// placed on XCD L % 8. Every XCD gets a contiguous band of (z-chunk, tile) items, and
-// within the band the widths of one item are adjacent, so the input planes they share
-// are read through one L2.
-__device__ __forceinline__ bool map_block(const FilterArgs& A, int& widx, int& item) {
+// placed on XCD L % 8. Every XCD gets a contiguous band of (z-chunk, tile) items, so the
+// input planes that neighbouring tiles share are read through one L2.
+__device__ __forceinline__ bool map_block(const FilterArgs& A, int& item) {
   const int L = blockIdx.x;
   const int xcd = L & 7;
-  const int r = L >> 3;
-  widx = r % A.nw;
-  const int j = r / A.nw;
+  const int j = L >> 3;
   item = xcd * A.tiles_per_xcd + j;
   return j < A.tiles_per_xcd && item < A.ntiles * A.nzc;
 }

@@ -9,12 +9,6 @@ namespace kcf {
 constexpr int kMaxR = 12;                 // largest stencil radius on the GPU
 constexpr int kMaxTaps = 2 * kMaxR + 1;
 constexpr int kNStat = 40;                // FP64 sums per filter width
-constexpr int kCX = 18, kCY = 14;         // computed columns of a tile (1-cell FD halo)
-constexpr int kOX = kCX - 2, kOY = kCY - 2;  // output columns of a tile
-constexpr int kNCol = kCX * kCY;          // 252 columns, two threads each
-constexpr int kNT = 2 * kNCol;            // 504 threads per workgroup (8 waves)
-constexpr int kStatWaves = (kNCol + 63) / 64;  // waves holding the column owners (4)
-constexpr int kYP = kCY / 2;              // rows per task of the y pass
 
 // Slots of the per-width FP64 sums.
 enum StatSlot {
@@ -23,9 +17,7 @@ enum StatSlot {
   S_PISM = 39
 };
 
-struct WidthArgs {
-  float w[kMaxTaps];      // taps w_{-R..R} of this width, zero padded to the kernel radius
-  double wd[kMaxTaps];    // the same taps in double (FP64 accumulation)
+struct WidthArgs {          // outputs, closure constants and statistics of one width
   float* rho_bar;
   float* ut;
   float* tau;
@@ -43,7 +35,7 @@ struct WidthArgs {
   float half_dt;          // dt / 2 of the shifted rate
   int gm_form;            // 0: G G^T, 1: G^T G
   int ksgs_rho_ref;       // 0: rho_bar, 1: 1
-  double* partials;       // [blocks][kStatWaves][kNStat] FP64 partial sums
+  double* partials;       // [records][kNStat] FP64 partial sums (one record per wave), or NULL
 };
 
 struct FilterArgs {
@@ -56,8 +48,7 @@ struct FilterArgs {
   int nzc, zlen;          // z chunks per column and their length
   int tiles_per_xcd;      // tiles of one XCD's contiguous band
   int strip_w;            // tile numbering: strips of strip_w tiles, or plain rows when 0
-  int nw;                 // widths in this launch
-  WidthArgs wa[4];
+  WidthArgs wa;
 };
 
 struct ClosureArgs {        // standalone gradient/closure pass from stored fields
@@ -70,6 +61,22 @@ struct ClosureArgs {        // standalone gradient/closure pass from stored fiel
   WidthArgs wa;
 };
 
+struct TapArgs {           // general-tap filter (kcf_taps.hip)
+  const float* rho;
+  const float* u;
+  int nx, ny, nz;
+  int64_t ntot;
+  int ntx, nty;            // 16x16 tiles of the x-y pass
+  int zb, nbuf;            // slab buffer: planes zb .. zb + nbuf - 1 (mod nz)
+  int zo0, zo1;            // output planes of the z pass
+  void* xy;                // slab buffer [10][nbuf][ny][nx], float or double
+  float w[kMaxTaps];       // taps w_{-R..R}
+  double wd[kMaxTaps];
+  float* rho_bar;          // outputs, each may be NULL
+  float* ut;
+  float* tau;
+};
+
 struct InputStatArgs {
   const float* rho;
   const float* u;
@@ -80,18 +87,21 @@ struct InputStatArgs {
 };
 
 // launchers (kcf_filter.hip)
-hipError_t launch_filter(const FilterArgs& a, const int* radii, const int* fp64, int nblocks,
-                         hipStream_t s);
-bool fp64_supported(int kernel_radius);
-hipError_t launch_grad_closure(const ClosureArgs& a, int* nblocks, hipStream_t s);
-int grad_closure_blocks(int64_t ntot);
+int64_t grad_closure_records(const ClosureArgs& a);  // per-wave partial records
+hipError_t launch_grad_closure(const ClosureArgs& a, hipStream_t s);
 int64_t input_stats_records(const InputStatArgs& a);  // per-wave partial records
 hipError_t launch_input_stats(const InputStatArgs& a, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nparts, int nstat, double* out,
                          hipStream_t s);
 hipError_t launch_reduce_check(const float* a, const float* b, int64_t n, double* partials,
                                int nblocks, hipStream_t s);
-int kernel_radius_for(int r);   // radius of the kernel instance used for stencil radius r
+
+// general-tap kernels (kcf_taps.hip)
+constexpr size_t kTapBufferCap = (size_t)8 << 30;  // bytes of x-y filtered planes held at once
+int taps_tile_x();
+int taps_tile_y();
+int taps_z_planes(int fp64);
+hipError_t launch_taps(const TapArgs& a, int R, int fp64, hipStream_t s);
 
 // box kernels (kcf_box.hip)
 struct BoxGeom {

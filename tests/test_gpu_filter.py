@@ -365,5 +365,29 @@ def test_c256_gauss8_sampled(ctx):
 
 
 def test_c512_box_multi_sampled(ctx):
-    say("[gpu] 512^3 box 2,4,8,16h fused: sampled-point parity")
+    say("[gpu] 512^3 box 2,4,8,16h: sampled-point parity")
     check_sampled(ctx, "c512_box_multi", 512, [(F.BOX, 2), (F.BOX, 4), (F.BOX, 8), (F.BOX, 16)], 12, 2)
+
+
+def test_c512_gauss4_fp64_slabs_sampled(ctx):
+    """Gaussian 4h at 512^3 accumulates in FP64: the x-y filtered products of the whole field
+    (10.7 GB) exceed the slab buffer, so the general-tap path runs slab by slab."""
+    say("[gpu] 512^3 gaussian delta=4h FP64 in z slabs: sampled-point parity")
+    check_sampled(ctx, "c512_box_multi", 512, [(F.GAUSS, 4)], 12, 3)
+
+
+@pytest.mark.parametrize("kind,nd,prec", [(F.BOX, 20, 0), (F.BOX, 12, 2), (F.GAUSS, 8, 2),
+                                          (F.GAUSS, 3, 0), (F.GAUSS, 6, 1)])
+def test_general_tap_widths(ctx, kind, nd, prec):
+    """Widths outside the sliding-sum kernel (box beyond R = 8, FP64 beyond R = 4, FP64
+    Gaussian at R = 12, odd Gaussian widths) run through the general-tap filter. (FP32 sums
+    at widths of 4h and below miss the tolerance; that is why the automatic choice is FP64
+    there.)"""
+    say(f"[gpu] general-tap width kind={kind} n={nd} precision={prec}")
+    rho, u = synth.workload_fields("c512_box_multi", n=32)
+    rho, u = rho.numpy(), u.numpy()
+    h = 2 * math.pi / 32
+    gpu, st = run_gpu(ctx, rho, u, h, [(kind, nd, prec)])
+    ora = F.full_path(rho, u, kind, nd, h)
+    check_fields(gpu[0], oracle_as_gpu_layout(ora))
+    check_stats(st[0], ora)
