@@ -61,7 +61,9 @@ struct BoxLds {
   static constexpr int HXP = HX | 1;
   static constexpr int NRAW = HX * HY;
   static constexpr int prod = (10 * HY * HXP * (int)sizeof(T) + 15) / 16 * 16;
-  static constexpr int su = 9 * C::BN * 4;  // ut of three planes
+  static constexpr int NI = kBOX * C::BOY;  // interior (output) columns
+  // ut of three planes, then rho_bar and tau of the interior columns of two planes
+  static constexpr int su = (9 * C::BN + 14 * NI) * 4;
   static constexpr int bytes = prod + su;
   static constexpr int doubles = (bytes + 7) / 8;
   // resident workgroups per CU: the smaller of the register and the LDS limit
@@ -113,7 +115,9 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   constexpr int NPF = (NRAW + kBT - 1) / kBT;
   constexpr int QS = HY * HXP;  // stride of one quantity in the buffer
   T* buf = reinterpret_cast<T*>(smem);
+  constexpr int NI = L::NI;
   float* su = reinterpret_cast<float*>(smem + L::prod);  // 3 planes x 3 x kBN
+  float* lagb = su + 9 * kBN;                             // 2 planes x 7 x NI
   const T inv_n = (T)1 / (T)(2 * R);
   const double inv_2n = 1.0 / (4.0 * R);
 
@@ -171,7 +175,6 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   double B[10];  // boxcar sums of the 2R planes za - 2R + 1 .. za
 #pragma unroll
   for (int q = 0; q < 10; ++q) B[q] = 0.0;
-  float lag_rb = 1.f, lag_tau[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   StatAcc acc;
   stat_zero(acc);
   const bool need_grad = needs_gradient(W);
@@ -258,11 +261,11 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
     }
     const int zo = za - R;
     const int us = (k - 2 * R + 3) % 3;
-    float cur_rb = 1.f, cur_tau[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (full) {  // uniform
       const double rinv = 1.0 / qb[0];
       const double uT[3] = {qb[1] * rinv, qb[2] * rinv, qb[3] * rinv};
-      cur_rb = (float)qb[0];
+      const float cur_rb = (float)qb[0];
+      float cur_tau[6];
       // tau_ij = bar(rho u_i u_j) - bar(rho u_i) ut_j
       cur_tau[0] = (float)fma(-qb[1], uT[0], qb[4]);
       cur_tau[1] = (float)fma(-qb[1], uT[1], qb[5]);
@@ -273,6 +276,12 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
       if (col_thread) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) su[(us * 3 + i) * kBN + col] = (float)uT[i];
+      }
+      if (interior) {  // for the gradient epilogue of the next step
+        float* lg = lagb + (k & 1) * 7 * NI + (cy - 1) * kBOX + (cx - 1);
+        lg[0] = cur_rb;
+#pragma unroll
+        for (int s = 0; s < 6; ++s) lg[(1 + s) * NI] = cur_tau[s];
       }
       if (interior && zo >= z0 && zo < z1) {
         const int64_t g = (int64_t)zo * plane + (int64_t)gy * A.nx + gx;
@@ -291,43 +300,38 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
     // overwrites it, and the velocity of plane zo is in LDS before the gradient reads it
     __syncthreads();
     const int zg = zo - 1;
-    if (need_grad && k >= 2 * R + 1 && zg >= z0 && zg < z1) {  // uniform
-      // ---- epilogue B: gradient, closures, statistics of plane zg
+    // ---- epilogue B: gradient, closures, statistics of plane zg, one interior column per
+    // thread (the waves past the NI interior columns have nothing to do)
+    if (need_grad && k >= 2 * R + 1 && zg >= z0 && zg < z1 && (tid & ~63) < NI) {  // uniform
       const int sg = (us + 2) % 3, sm = (us + 1) % 3, sp = us;
+      const int t = tid < NI ? tid : 0;
+      const int ex = 1 + t % kBOX, ey = 1 + t / kBOX;
+      const int ecol = ey * kBX + ex;
+      const int egx = x0 + ex, egy = y0 + ey;
+      const bool valid = tid < NI && egx < A.nx && egy < A.ny;
+      const float* lg = lagb + ((k - 1) & 1) * 7 * NI + t;
+      const float rb = lg[0];
+      float tau[6];
+#pragma unroll
+      for (int s = 0; s < 6; ++s) tau[s] = lg[(1 + s) * NI];
       PointOut P;
-      float u[3] = {0.f, 0.f, 0.f};
-      if (interior) {
-        const float* uc = su + sg * 3 * kBN;
+      float u[3];
+      const float* uc = su + sg * 3 * kBN;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const float* ui = uc + i * kBN;
-          P.G[i][0] = (ui[col + 1] - ui[col - 1]) * A.inv2h;
-          P.G[i][1] = (ui[col + kBX] - ui[col - kBX]) * A.inv2h;
-          P.G[i][2] = (su[(sp * 3 + i) * kBN + col] - su[(sm * 3 + i) * kBN + col]) * A.inv2h;
-          u[i] = ui[col];
-        }
-        point_closures(W, lag_rb, lag_tau, P);
-        const int64_t g = (int64_t)zg * plane + (int64_t)gy * A.nx + gx;
-        store_point(W, g, ntot, P);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j) P.G[i][j] = 0.f;
-#pragma unroll
-        for (int s = 0; s < 6; ++s) P.tgm[s] = P.tsm[s] = 0.f;
-        P.ksgs = P.nut = P.omt = 0.f;
+      for (int i = 0; i < 3; ++i) {
+        const float* ui = uc + i * kBN;
+        P.G[i][0] = (ui[ecol + 1] - ui[ecol - 1]) * A.inv2h;
+        P.G[i][1] = (ui[ecol + kBX] - ui[ecol - kBX]) * A.inv2h;
+        P.G[i][2] = (su[(sp * 3 + i) * kBN + ecol] - su[(sm * 3 + i) * kBN + ecol]) * A.inv2h;
+        u[i] = ui[ecol];
       }
+      point_closures(W, rb, tau, P);
+      if (valid) store_point(W, (int64_t)zg * plane + (int64_t)egy * A.nx + egx, ntot, P);
       if (W.partials) {  // uniform
         StatIn I;
-        stat_inputs(lag_rb, u, lag_tau, P, interior, I);
+        stat_inputs(rb, u, tau, P, valid, I);
         stat_add(I, acc);
       }
-    }
-    if (full) {
-      lag_rb = cur_rb;
-#pragma unroll
-      for (int s = 0; s < 6; ++s) lag_tau[s] = cur_tau[s];
     }
   }
   if (W.partials) write_stats(W.partials + ((int64_t)item * (kBT / 64) + (tid >> 6)) * kNStat, acc);

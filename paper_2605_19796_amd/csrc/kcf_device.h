@@ -103,8 +103,9 @@ __device__ __forceinline__ void stat_inputs(float rb, const float (&u)[3], const
   double pi = 0, pigm = 0, pism = 0;
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
-    const double S = 0.5 * ((double)P.G[ii[s]][jj[s]] + (double)P.G[jj[s]][ii[s]]);
-    const double m = (ii[s] == jj[s]) ? S : 2.0 * S;
+    // S_ij counted for (i,j) and (j,i): G_ii on the diagonal, G_ij + G_ji off it (exact)
+    const double m = (ii[s] == jj[s]) ? (double)P.G[ii[s]][ii[s]]
+                                      : (double)P.G[ii[s]][jj[s]] + (double)P.G[jj[s]][ii[s]];
     pi -= (double)tau[s] * m;
     pigm -= (double)P.tgm[s] * m;
     pism -= (double)P.tsm[s] * m;
