@@ -262,6 +262,27 @@ def test_training_beats_gradient_model(ctx):
         f"fallback {res['fallback']}/{res['n']}")
     assert res["r_learned_mean"] >= 0.9
     assert res["nrmse_learned_mean"] < res["nrmse_gm_mean"]
+    # precision of the BF16 MFMA inference: the same trained network in FP64 without BF16
+    # rounding (oracle), on held-out points inside the envelope, per tau component
+    o, st = learned.filtered_fields(ctx, rho_t, u_t, h, kcf.GAUSS, 8)
+    Xt, _ = kcf.mlp_features(ctx, o["rho_bar"], o["ut"], o["tau"], h, 8 * h)
+    mask = torch.zeros((n ** 3 + 15) // 16, dtype=torch.int16, device="cuda")
+    tau_l, _ = m.infer_field(o["rho_bar"], o["ut"], h, 8 * h, st["m2"], mask_out=mask)
+    bits = mask.cpu().numpy().view(np.uint16)
+    flag = ((bits[:, None] >> np.arange(16)) & 1).astype(bool).reshape(-1)[: n ** 3]
+    rng = np.random.default_rng(5)
+    idx = rng.choice(np.flatnonzero(~flag), 50000, replace=False)
+    nm = m.get_norm()
+    xs = std32(Xt.cpu().numpy()[idx], nm[:14], nm[14:28]).astype(np.float64)
+    y64, _ = M.forward(m.get_params().astype(np.float64), xs, bf16=False)
+    rb = o["rho_bar"].cpu().numpy().reshape(-1)[idx].astype(np.float64)
+    t64 = rb[:, None] * (nm[28:34] + nm[34:40] * y64)
+    tg = tau_l.cpu().numpy().reshape(6, -1)[:, idx].T.astype(np.float64)
+    emax = np.max(np.abs(tg - t64), 0) / np.max(np.abs(t64), 0)
+    erms = np.sqrt(np.mean((tg - t64) ** 2, 0) / np.mean(t64 ** 2, 0))
+    say("[gpu]   BF16 inference vs FP64 network, per component (xx xy xz yy yz zz): max "
+        + " ".join(f"{v:.2e}" for v in emax) + "; rms " + " ".join(f"{v:.2e}" for v in erms))
+    assert np.all(erms <= 1e-2) and np.all(emax <= 2e-2)
     m.close()
 
 
