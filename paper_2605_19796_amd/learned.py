@@ -1,9 +1,9 @@
 """Driver of the learned closure: dataset from filtered fields, training loop, evaluation.
 
 Orchestration only: every arithmetic step (filtering, features, statistics, forward and
-backward passes, Adam, inference) runs in libkcf. Random numbers the training draws (the
-initial parameters and the per-epoch sample order) come from a seeded numpy generator on
-the host and are handed to the library as inputs.
+backward passes, Adam, inference) runs in libkcf. Random numbers the training draws are
+handed to the library as inputs: the initial parameters come from a seeded numpy generator
+on the host, the per-epoch sample order from a seeded torch generator on the device.
 """
 from __future__ import annotations
 
@@ -55,8 +55,9 @@ def train(mlp, X, Y, steps, batch=65536, lr=1e-3, lr_final=1e-4, seed=7, loss_ev
     """Minibatch Adam over the dataset; epochs draw a fresh permutation. Returns the loss
     history (step, loss) read back every `loss_every` steps."""
     n = X.shape[0]
-    rng = np.random.default_rng(seed)
     dev = X.device
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
     losses = torch.zeros(steps, dtype=torch.float32, device=dev)
     per_epoch = max(n // batch, 1)
     perm = None
@@ -64,7 +65,7 @@ def train(mlp, X, Y, steps, batch=65536, lr=1e-3, lr_final=1e-4, seed=7, loss_ev
     for s in range(steps):
         e = s % per_epoch
         if e == 0:
-            perm = torch.from_numpy(rng.permutation(n)[: per_epoch * batch].astype(np.int32)).to(dev)
+            perm = torch.randperm(n, generator=gen, device=dev)[: per_epoch * batch].to(torch.int32)
         idx = perm[e * batch:(e + 1) * batch]
         frac = s / max(steps - 1, 1)
         cur = lr * (lr_final / lr) ** frac
