@@ -1,0 +1,94 @@
+"""FP64 oracle: the a priori D3Q27 SGS carrier f_sgs,i = bar(f0_i(rho, u)) - f0_i(rho_bar, ut)
+and its second-order Hermite reconstruction from tau.
+
+TEST INFRASTRUCTURE. Only the tests and the smoke check may import this module; the product
+path never calls it. It shares no code with the HIP library.
+
+Definitions (paper: Sec. "Filtered nondimensional recorrelated BGK-BE", eqs. f0bar, fsgs_def;
+App. "Lattice-Boltzmann discretization", eq. discrete_equilibrium; App. "Hermite
+representation" and the KC-MP closure, eq. f_sgs_KCMP):
+
+* D3Q27 velocities xi_i in {-1, 0, 1}^3 (lattice units), weights w_i = prod of the D1Q3
+  weights (2/3 for 0, 1/6 for +-1), reference temperature theta_R = 1/3.
+* Velocities of the fields are given in units of sqrt(theta_R) (Mach numbers, the units of
+  the synthetic inputs); with xh = xi / sqrt(theta_R) in {0, +-sqrt(3)} the product
+  equilibrium reads f0_i(rho, u) = w_i rho prod_a (1 + xh_ia u_a + (xh_ia^2 - 1) u_a^2 / 2).
+* Exact carrier: f_sgs,i = bar(f0_i(rho, u)) - f0_i(rho_bar, ut), the filter applied to each
+  of the 27 equilibria.
+* Second-order Hermite reconstruction: f_h2,i = w_i / 2 * sum_ab H_iab tau_ab,
+  H_iab = xh_ia xh_ib - delta_ab, with tau in the same units.
+
+Parity status: pinned by the moment identities (sum f_sgs = 0, sum xh f_sgs = 0,
+sum xh xh f_sgs = tau of the field oracle), vanishing on constant and uniform-velocity fields,
+exactness of the reconstruction for a one-component velocity at unit density, and the
+brute-force lattice equilibrium against its moment form.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+import numpy as np
+
+from . import fields as F
+
+W1 = {0: 2.0 / 3.0, 1: 1.0 / 6.0, -1: 1.0 / 6.0}
+SQ3 = math.sqrt(3.0)
+
+
+def lattice():
+    """(xi (27, 3) integers, xh (27, 3) = xi sqrt(3), w (27,)) in the order of itertools.product
+    over (x, y, z) in (-1, 0, 1)."""
+    xi = np.array(list(itertools.product((-1, 0, 1), repeat=3)), dtype=np.int64)
+    w = np.array([W1[a] * W1[b] * W1[c] for a, b, c in xi])
+    return xi, xi * SQ3, w
+
+
+def equilibrium(rho, u):
+    """f0_i(rho, u) of every population, shape (27,) + rho.shape (eq. discrete_equilibrium)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    _, xh, w = lattice()
+    out = np.empty((27,) + rho.shape)
+    for i in range(27):
+        f = w[i] * rho
+        for a in range(3):
+            f = f * (1.0 + xh[i, a] * u[a] + 0.5 * (xh[i, a] ** 2 - 1.0) * u[a] ** 2)
+        out[i] = f
+    return out
+
+
+def moments(f):
+    """Zeroth, first and second moments of populations f (27, ...) in xh units."""
+    _, xh, _ = lattice()
+    m0 = f.sum(0)
+    m1 = np.einsum("ia,i...->a...", xh, f)
+    m2 = np.einsum("ia,ib,i...->ab...", xh, xh, f)
+    return m0, m1, m2
+
+
+def hermite2(tau):
+    """f_h2,i = w_i / 2 sum_ab (xh_ia xh_ib - delta_ab) tau_ab; tau (3, 3, ...)."""
+    _, xh, w = lattice()
+    H = np.einsum("ia,ib->iab", xh, xh) - np.eye(3)[None]
+    return 0.5 * w.reshape((27,) + (1,) * (tau.ndim - 2)) * np.einsum("iab,ab...->i...", H, tau)
+
+
+def carrier(rho, u, kind: int, n_delta: int, separable=True):
+    """Exact carrier, its Hermite reconstruction and the Favre fields of one filter width."""
+    w, _ = F.filter_weights(kind, n_delta)
+    f0 = equilibrium(rho, u)
+    filt = F.filter_separable if separable else F.filter_direct
+    f0bar = np.stack([filt(f0[i], w) for i in range(27)])
+    rho_bar, ut, tau = F.filter_favre(rho, u, w, separable=separable)
+    f_sgs = f0bar - equilibrium(rho_bar, ut)
+    f_h2 = hermite2(tau)
+    return dict(f_sgs=f_sgs, f_h2=f_h2, rho_bar=rho_bar, ut=ut, tau=tau)
+
+
+def carrier_stats(f_sgs, f_h2):
+    """<sum_i f_sgs,i^2>, <sum_i (f_sgs,i - f_h2,i)^2> and their ratio's square root (the
+    relative L2 error of the second-order reconstruction)."""
+    e2 = float(np.mean(np.sum((f_sgs - f_h2) ** 2, 0)))
+    s2 = float(np.mean(np.sum(f_sgs ** 2, 0)))
+    return dict(sgs_l2=s2, err_l2=e2, rel_err=math.sqrt(e2 / s2) if s2 > 0 else 0.0)
