@@ -18,10 +18,15 @@ representation" and the KC-MP closure, eq. f_sgs_KCMP):
 * Second-order Hermite reconstruction: f_h2,i = w_i / 2 * sum_ab H_iab tau_ab,
   H_iab = xh_ia xh_ib - delta_ab, with tau in the same units.
 
+* Hermite-order energies: f projected on the tensor-product D1Q3 Hermite basis by lattice
+  quadrature; E_n is the weighted energy of the terms of total degree n.
+
 Parity status: pinned by the moment identities (sum f_sgs = 0, sum xh f_sgs = 0,
 sum xh xh f_sgs = tau of the field oracle), vanishing on constant and uniform-velocity fields,
 exactness of the reconstruction for a one-component velocity at unit density, and the
-brute-force lattice equilibrium against its moment form.
+brute-force lattice equilibrium against its moment form; the Hermite energies by Parseval,
+by E_2 against tau of the field oracle, by vanishing E_0, E_1 of the carrier and by single
+basis functions of known norm.
 """
 from __future__ import annotations
 
@@ -86,9 +91,35 @@ def carrier(rho, u, kind: int, n_delta: int, separable=True):
     return dict(f_sgs=f_sgs, f_h2=f_h2, rho_bar=rho_bar, ut=ut, tau=tau)
 
 
+def hermite_coefficients(f):
+    """Coefficients d_abc (a, b, c in 0..2; shape (3, 3, 3) + point shape) of populations f in
+    the tensor-product D1Q3 Hermite basis P_0 = 1, P_1 = xh, P_2 = (xh^2 - 1)/2, by quadrature:
+    d_abc = sum_i f_i P_a(xh_ix) P_b(xh_iy) P_c(xh_iz) / (n_a n_b n_c) with the norms
+    n_a = sum_k w_k P_a(xh_k)^2 = (1, 1, 1/2). Their total degree a + b + c is the Hermite
+    order of the term (the expansion of eq. f_sgs_hermite, truncated to the lattice)."""
+    _, xh, _ = lattice()
+    P = np.stack([np.ones_like(xh), xh, 0.5 * (xh ** 2 - 1.0)])  # (3 degrees, 27, 3 dims)
+    nrm = np.array([1.0, 1.0, 0.5])
+    d = np.einsum("ai,bi,ci,i...->abc...", P[:, :, 0], P[:, :, 1], P[:, :, 2], f)
+    return d / np.einsum("a,b,c->abc", nrm, nrm, nrm).reshape((3, 3, 3) + (1,) * (f.ndim - 1))
+
+
+def hermite_energies(f):
+    """E_n = <sum_{a+b+c=n} n_a n_b n_c d_abc^2>, n = 0..6: the split of the weighted energy
+    <sum_i f_i^2 / w_i> over the Hermite orders of f (Parseval under the lattice weights)."""
+    d = hermite_coefficients(f)
+    nrm = np.array([1.0, 1.0, 0.5])
+    out = np.zeros(7)
+    for a, b, c in itertools.product(range(3), repeat=3):
+        out[a + b + c] += nrm[a] * nrm[b] * nrm[c] * float(np.mean(d[a, b, c] ** 2))
+    return out
+
+
 def carrier_stats(f_sgs, f_h2):
-    """<sum_i f_sgs,i^2>, <sum_i (f_sgs,i - f_h2,i)^2> and their ratio's square root (the
-    relative L2 error of the second-order reconstruction)."""
+    """<sum_i f_sgs,i^2>, <sum_i (f_sgs,i - f_h2,i)^2>, their ratio's square root (the
+    relative L2 error of the second-order reconstruction) and the Hermite-order energies of
+    f_sgs."""
     e2 = float(np.mean(np.sum((f_sgs - f_h2) ** 2, 0)))
     s2 = float(np.mean(np.sum(f_sgs ** 2, 0)))
-    return dict(sgs_l2=s2, err_l2=e2, rel_err=math.sqrt(e2 / s2) if s2 > 0 else 0.0)
+    return dict(sgs_l2=s2, err_l2=e2, rel_err=math.sqrt(e2 / s2) if s2 > 0 else 0.0,
+                hermite=hermite_energies(f_sgs))

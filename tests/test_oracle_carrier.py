@@ -88,3 +88,42 @@ def test_carrier_separable_equals_direct():
     a = K.carrier(rho, u, F.BOX, 2)["f_sgs"]
     b = K.carrier(rho, u, F.BOX, 2, separable=False)["f_sgs"]
     assert np.max(np.abs(a - b)) < 1e-15
+
+
+def test_hermite_energies_of_basis_functions():
+    """A single basis term w_i P_a P_b P_c has all its energy n_a n_b n_c in order a + b + c."""
+    _, xh, w = K.lattice()
+    P = [np.ones(27), None, None]
+    nrm = [1.0, 1.0, 0.5]
+    for a, b, c in [(0, 0, 0), (1, 0, 0), (0, 2, 0), (1, 1, 1), (2, 0, 2), (2, 2, 2)]:
+        fac = []
+        for deg, dim in zip((a, b, c), range(3)):
+            x = xh[:, dim]
+            fac.append([np.ones(27), x, 0.5 * (x * x - 1.0)][deg])
+        f = (w * fac[0] * fac[1] * fac[2])[:, None]
+        e = K.hermite_energies(f)
+        expect = np.zeros(7)
+        expect[a + b + c] = nrm[a] * nrm[b] * nrm[c]
+        assert np.allclose(e, expect, atol=1e-14), (a, b, c, e)
+
+
+def test_hermite_energies_of_the_carrier():
+    """Parseval under the lattice weights; no energy in orders 0 and 1 (vanishing zeroth and
+    first moments); order 2 carries sum_a tau_aa^2 / 2 + sum_{a<b} tau_ab^2 with tau from the
+    field oracle; the reconstruction holds exactly the order-2 part."""
+    rho, u = synth.random_fields((10, 12, 8), seed=6, rho_amp=0.2)
+    r = K.carrier(rho, u, F.GAUSS, 2)
+    _, _, w = K.lattice()
+    e = K.hermite_energies(r["f_sgs"])
+    total = float(np.mean(np.sum(r["f_sgs"] ** 2 / w[:, None, None, None], 0)))
+    assert abs(e.sum() - total) < 1e-13 * total
+    assert e[0] < 1e-25 * total and e[1] < 1e-25 * total
+    _, _, tau = F.filter_favre(rho, u, F.filter_weights(F.GAUSS, 2)[0])
+    e2 = float(np.mean(0.5 * (tau[0, 0] ** 2 + tau[1, 1] ** 2 + tau[2, 2] ** 2)
+                       + tau[0, 1] ** 2 + tau[0, 2] ** 2 + tau[1, 2] ** 2))
+    assert abs(e[2] - e2) < 1e-12 * e2
+    assert min(e[3], e[4]) > 0
+    h = K.hermite_energies(r["f_h2"])
+    assert abs(h[2] - e[2]) < 1e-12 * e[2] and h.sum() - h[2] < 1e-25 * total
+    d = K.hermite_energies(r["f_sgs"] - r["f_h2"])
+    assert abs(d.sum() - e[3:].sum()) < 1e-12 * total and d[2] < 1e-25 * total
