@@ -106,6 +106,20 @@ typedef struct {
   double raw[40];               /* the raw FP64 sums the above are derived from */
 } kcf_width_stats;
 
+/* Statistics of the SGS carrier (kcf_sgs_carrier), means over the finite points: each
+ * point's sums over its 27 populations in FP32, their sums over points in FP64. */
+typedef struct {
+  double sgs_l2;                /* <sum_i f_sgs,i^2> */
+  double err_l2;                /* <sum_i (f_sgs,i - f_h2,i)^2> */
+  double rel_err;               /* sqrt(err_l2 / sgs_l2): relative L2 error of f_h2 */
+  double hermite[5];            /* <E_n>, n = 2..6: weighted energy sum_i f_i^2 / w_i of the
+                                   Hermite terms of order n (E_0 = E_1 = 0 exactly) */
+  int64_t n_points;             /* points counted (finite outputs) */
+  int64_t n_nonfinite;          /* points with a non-finite output (excluded from sums) */
+  double raw[9];                /* the raw FP64 sums: count, sum f^2, sum (f - f_h2)^2,
+                                   E_2..E_6, non-finite count */
+} kcf_carrier_stats;
+
 typedef struct {
   double mean_rho;              /* <rho> */
   double ek;                    /* <rho |u|^2 / 2> */
@@ -168,6 +182,29 @@ int kcf_filter_favre(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filte
 int kcf_grad_closure(kcf_ctx *ctx, const kcf_grid *grid, const float *rho_bar, const float *ut,
                      const float *tau, double delta, double m2, const kcf_closure_params *cp,
                      const kcf_outputs *outs, kcf_width_stats *stats);
+
+/* A priori SGS carrier of the D3Q27 lattice for one filter width: the residual
+ *   f_sgs,i = bar(f0_i(rho, u)) - f0_i(rho_bar, ut)
+ * of filtering the equilibrium (Sec. "Filtered nondimensional recorrelated BGK-BE",
+ * eqs. f0bar and fsgs_def), with the product equilibrium of App. "Lattice-Boltzmann
+ * discretization" (eq. discrete_equilibrium), and its second-order Hermite reconstruction
+ *   f_h2,i = w_i / 2 (xh_ia xh_ib - delta_ab) tau_ab
+ * of the KC-MP closure (Sec. "Moment-Projected Closure (KC-MP)", eq. f_sgs_KCMP).
+ * Units: velocities u in units of sqrt(theta_R) (Mach numbers); xh_i = xi_i / sqrt(theta_R) in
+ * {0, +-sqrt(3)}^3 for the lattice velocities xi_i in {-1, 0, 1}^3; w_i = product of the D1Q3
+ * weights 2/3 (0) and 1/6 (+-1); populations in units of density. Population i is
+ * xi_i = (c_x, c_y, c_z) with i = 9 (c_x + 1) + 3 (c_y + 1) + (c_z + 1).
+ * f_sgs and f_h2 (device, 27 N floats each, population blocks [i][N]) and stats (host) may
+ * each be NULL, but not all three. filter->precision as for kcf_filter_favre (auto: FP64 for
+ * widths up to 4h). The call filters the 27 monomials rho u_x^a u_y^b u_z^c (a, b, c <= 2)
+ * in z slabs through a context buffer of at most 8 GiB and launches two kernels per slab
+ * (both timed when timing is on); with stats it synchronises.
+ * Errors: KCF_EINVAL for null rho/u/grid/filter, nothing requested, bad filter or n < 3;
+ * KCF_EUNSUPPORTED when 2R+1 exceeds a grid dimension, R > 12 or ny > 65535; KCF_ENOMEM when a
+ * context buffer cannot be allocated. */
+int kcf_sgs_carrier(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filter,
+                    const float *rho, const float *u, float *f_sgs, float *f_h2,
+                    kcf_carrier_stats *stats);
 
 /* E_k, enstrophy and <rho> of the unfiltered input (synchronises). */
 int kcf_input_stats(kcf_ctx *ctx, const kcf_grid *grid, const float *rho, const float *u,

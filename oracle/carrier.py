@@ -91,6 +91,30 @@ def carrier(rho, u, kind: int, n_delta: int, separable=True):
     return dict(f_sgs=f_sgs, f_h2=f_h2, rho_bar=rho_bar, ut=ut, tau=tau)
 
 
+def carrier_at(rho, u, kind: int, n_delta: int, pts):
+    """f_sgs and f_h2 (each (npts, 27)) at points (k, j, i) by direct 3-D sums of the 27
+    equilibria over each point's (2R+1)^3 neighbourhood, for grids too large for carrier()."""
+    w, R = F.filter_weights(kind, n_delta)
+    rho = np.asarray(rho)
+    u = np.asarray(u)
+    nz, ny, nx = rho.shape
+    w3 = np.einsum("a,b,c->abc", w, w, w)
+    offs = np.arange(-R, R + 1)
+    fs, fh = [], []
+    for (k, j, i) in np.asarray(pts).reshape(-1, 3):
+        ix = np.ix_((k + offs) % nz, (j + offs) % ny, (i + offs) % nx)
+        r = rho[ix].astype(np.float64)
+        uu = np.stack([u[a][ix] for a in range(3)]).astype(np.float64)
+        f0bar = np.array([np.sum(w3 * f) for f in equilibrium(r, uu)])
+        rb = float(np.sum(w3 * r))
+        ut = np.array([np.sum(w3 * r * uu[a]) for a in range(3)]) / rb
+        tau = np.array([[np.sum(w3 * r * uu[a] * uu[b]) for b in range(3)] for a in range(3)])
+        tau = tau - rb * np.outer(ut, ut)
+        fs.append(f0bar - equilibrium(np.array(rb), ut))
+        fh.append(hermite2(tau))
+    return np.array(fs), np.array(fh)
+
+
 def hermite_coefficients(f):
     """Coefficients d_abc (a, b, c in 0..2; shape (3, 3, 3) + point shape) of populations f in
     the tensor-product D1Q3 Hermite basis P_0 = 1, P_1 = xh, P_2 = (xh^2 - 1)/2, by quadrature:

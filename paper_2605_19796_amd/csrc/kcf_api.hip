@@ -514,6 +514,98 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
   return KCF_OK;
 }
 
+int kcf_sgs_carrier(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, const float* rho,
+                    const float* u, float* f_sgs, float* f_h2, kcf_carrier_stats* stats) {
+  if (!c) return fail(KCF_EINVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!filter || !rho || !u) return fail(KCF_EINVAL, "NULL argument");
+  if (!f_sgs && !f_h2 && !stats) return fail(KCF_EINVAL, "nothing requested");
+  Taps taps;
+  if ((rc = compute_taps(filter->kind, filter->delta_over_h, grid->h, taps))) return rc;
+  const int R = taps.R;
+  if (R > kMaxR) return fail(KCF_EUNSUPPORTED, "filter radius above 12 cells");
+  if (2 * R + 1 > std::min(grid->nx, std::min(grid->ny, grid->nz)))
+    return fail(KCF_EUNSUPPORTED, "filter support 2R+1 exceeds the grid");
+  const int p = filter->precision;
+  if (p < 0 || p > 2) return fail(KCF_EINVAL, "precision must be 0 (auto), 1 (fp32) or 2 (fp64)");
+  const int fp64 = p == 2 || (p == 0 && filter->delta_over_h <= 4);
+  if (grid->ny > 65535) return fail(KCF_EUNSUPPORTED, "ny above 65535");
+  KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  CarrierArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.rho = rho;
+  A.u = u;
+  A.nx = grid->nx;
+  A.ny = grid->ny;
+  A.nz = grid->nz;
+  A.ntot = (int64_t)grid->nx * grid->ny * grid->nz;
+  A.ntx = (grid->nx + carrier_tile_x() - 1) / carrier_tile_x();
+  A.nty = (grid->ny + carrier_tile_y() - 1) / carrier_tile_y();
+  A.ntiles = A.ntx * A.nty;
+  for (int m = 0; m < 2 * R + 1; ++m) {
+    A.wd[m] = taps.wd[m];
+    A.w[m] = (float)taps.wd[m];
+  }
+  A.f_sgs = f_sgs;
+  A.f_h2 = f_h2;
+  // z slabs whose 27 filtered monomials fit the buffer cap (the whole field if they can)
+  const int64_t plane = (int64_t)grid->nx * grid->ny;
+  const size_t per_plane = 27 * (size_t)plane * (fp64 ? sizeof(double) : sizeof(float));
+  const int zt = carrier_z_planes(fp64);
+  int slab = grid->nz;
+  if (per_plane * (size_t)grid->nz > kTapBufferCap)
+    slab = std::max(zt, (int)(kTapBufferCap / per_plane) / zt * zt);
+  if ((rc = ensure_buffer(c, c->d_xy, c->xy_cap, per_plane * (size_t)slab,
+                          "cannot allocate the carrier slab buffer")))
+    return rc;
+  A.zbuf = c->d_xy;
+  int64_t nrec = 0;  // statistics records of all slabs
+  for (int zs = 0; zs < grid->nz; zs += slab) {
+    A.nzs = std::min(slab, grid->nz - zs);
+    nrec += carrier_xy_records(A);
+  }
+  if (stats) {
+    if (nrec > INT32_MAX) return fail(KCF_EUNSUPPORTED, "grid too large for statistics");
+    if ((rc = ensure_partials(c, (size_t)nrec * kCStat))) return rc;
+  }
+  int64_t rec0 = 0;
+  for (int zs = 0; zs < grid->nz; zs += slab) {
+    A.zs = zs;
+    A.nzs = std::min(slab, grid->nz - zs);
+    A.partials = stats ? c->d_part + (size_t)rec0 * kCStat : nullptr;
+    rec0 += carrier_xy_records(A);
+    if ((rc = timed_begin(c))) return rc;
+    hipError_t e = launch_carrier_z(A, R, fp64, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "carrier z launch");
+    if ((rc = timed_end(c))) return rc;
+    if ((rc = timed_begin(c))) return rc;
+    e = launch_carrier_xy(A, R, fp64, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "carrier x-y launch");
+    if ((rc = timed_end(c))) return rc;
+  }
+  if (stats) {
+    hipError_t e = launch_reduce(c->d_part, (int)nrec, kCStat, c->d_sums, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * kCStat, hipMemcpyDeviceToHost,
+                           c->stream), "stats copy");
+    KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    const double* raw = c->h_sums;
+    std::memset(stats, 0, sizeof(*stats));
+    std::memcpy(stats->raw, raw, sizeof(double) * kCStat);
+    const double n = raw[C_N];
+    stats->n_points = (int64_t)llround(n);
+    stats->n_nonfinite = (int64_t)llround(raw[C_NONFINITE]);
+    if (n > 0) {
+      stats->sgs_l2 = raw[C_F2] / n;
+      stats->err_l2 = raw[C_ERR2] / n;
+      stats->rel_err = raw[C_F2] > 0 ? std::sqrt(raw[C_ERR2] / raw[C_F2]) : 0.0;
+      for (int k = 0; k < 5; ++k) stats->hermite[k] = raw[C_HERM + k] / n;
+    }
+  }
+  return KCF_OK;
+}
+
 int kcf_grad_closure(kcf_ctx* c, const kcf_grid* grid, const float* rho_bar, const float* ut,
                      const float* tau, double delta, double m2, const kcf_closure_params* cp,
                      const kcf_outputs* outs, kcf_width_stats* stats) {

@@ -1,0 +1,404 @@
+// A priori SGS carrier of the D3Q27 lattice: f_sgs,i = bar(f0_i(rho, u)) - f0_i(rho_bar, ut)
+// (eqs. f0bar and fsgs_def) with the product equilibrium of eq. discrete_equilibrium, and the
+// second-order Hermite reconstruction of the KC-MP closure from tau (eq. f_sgs_KCMP).
+//
+// With velocities in units of sqrt(theta_R) and xh = xi / sqrt(theta_R) in {0, +-sqrt3}, the
+// equilibrium is w_i rho prod_a (P_0 + P_1(xh_ia) u_a + P_2(xh_ia) u_a^2) with the D1Q3
+// Hermite polynomials P_0 = 1, P_1 = xh, P_2 = (xh^2 - 1)/2. The filter is linear, hence
+//   f_sgs,i = w_i sum_abc P_a(xh_ix) P_b(xh_iy) P_c(xh_iz) D_abc,
+//   D_abc   = bar(rho u_x^a u_y^b u_z^c) - rho_bar ut_x^a ut_y^b ut_z^c,     a, b, c in 0..2:
+// 27 filtered monomials replace 27 filtered populations, and the subtraction happens where
+// the cancellation is smallest. D vanishes at total degree <= 1 (definition of ut); the
+// degree-2 D are tau, whose terms alone form the reconstruction f_h2. The total degree is the
+// Hermite order of a term (eq. f_sgs_hermite on the tensor-product lattice).
+//
+// Two kernels per z slab:
+//   k_carrier_z   one thread per (x, y) column and ZT planes: the monomials of the input,
+//                 nine at a time (one power of u_z), filtered along z over a register window
+//                 of the input planes and written to the slab buffer [27][planes][ny][nx];
+//   k_carrier_xy  one workgroup per (kTX x kTY tile, run of eight planes), XCD-banded: per plane,
+//                 the monomials of the tile and its halo staged in LDS G at a time, filtered
+//                 along x and y in place, each thread keeping its point's 27 filtered
+//                 monomials; then D, the Hermite synthesis of f_sgs and f_h2, the stores and
+//                 the statistics (a point's sums over its populations in FP32, their sums over
+//                 points in FP64, one record per workgroup).
+// T is the type of the monomials, of both filter passes, of the slab buffer and of D (double
+// for narrow widths, as in the Favre path); the synthesis from D runs in FP32.
+#include "kcf_device.h"
+
+namespace kcf {
+
+namespace {
+
+using namespace dev;
+
+constexpr int kZB = 256;  // threads of k_carrier_z
+constexpr int kTX = 16;   // tile of k_carrier_xy: kTX x kTY points, one per thread
+constexpr int kTY = 16;
+constexpr int kXT = 256;  // threads of k_carrier_xy (one per tile point)
+constexpr int kLook = 3;  // input planes in flight ahead of the FMAs in k_carrier_z
+constexpr int kXZ = 8;    // planes per workgroup of k_carrier_xy
+
+template <typename T>
+constexpr int cz_planes() { return sizeof(T) == 8 ? 8 : 16; }
+
+template <typename T>
+__device__ __forceinline__ const T* cweights(const CarrierArgs& A);
+template <>
+__device__ __forceinline__ const float* cweights<float>(const CarrierArgs& A) { return A.w; }
+template <>
+__device__ __forceinline__ const double* cweights<double>(const CarrierArgs& A) { return A.wd; }
+
+// Monomial m = a + 3 b + 9 c stands for rho u_x^a u_y^b u_z^c.
+__host__ __device__ constexpr int mono_deg(int m) { return m % 3 + (m / 3) % 3 + m / 9; }
+// weighted norm n_a n_b n_c of the basis term, n = (1, 1, 1/2)
+__host__ __device__ constexpr double mono_norm(int m) {
+  return (m % 3 == 2 ? 0.5 : 1.0) * ((m / 3) % 3 == 2 ? 0.5 : 1.0) * (m / 9 == 2 ? 0.5 : 1.0);
+}
+
+// Loads of the input plane zz at the column of byte offset cb (< 2^32 since a plane holds at
+// most 2^30 points): uniform plane pointers plus a 32-bit per-lane offset.
+__device__ __forceinline__ void load_inputs(const CarrierArgs& A, int zz, uint32_t cb,
+                                            float (&v)[4]) {
+  const int64_t zo = (int64_t)zz * A.nx * A.ny;
+  const char* pr = reinterpret_cast<const char*>(A.rho + zo);
+  const char* pu = reinterpret_cast<const char*>(A.u + zo);
+  const int64_t nb = A.ntot * (int64_t)sizeof(float);
+  v[0] = *reinterpret_cast<const float*>(pr + cb);
+  v[1] = *reinterpret_cast<const float*>(pu + cb);
+  v[2] = *reinterpret_cast<const float*>(pu + nb + cb);
+  v[3] = *reinterpret_cast<const float*>(pu + 2 * nb + cb);
+}
+
+// Two waves per SIMD: the register budget then bounds how far the scheduler hoists the
+// window loads ahead of their FMAs.
+template <int R, typename T>
+__global__ void __launch_bounds__(kZB) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_carrier_z(CarrierArgs A) {
+  constexpr int ZT = cz_planes<T>();
+  constexpr int NJ = ZT + 2 * R;  // input planes z0 - R .. z0 + ZT + R - 1 of the window
+  const int x = blockIdx.x * kZB + threadIdx.x;
+  if (x >= A.nx) return;
+  const int y = blockIdx.y;
+  const int zl0 = blockIdx.z * ZT;  // first plane of the thread, relative to the slab
+  const int nk = min(ZT, A.nzs - zl0);
+  const int64_t plane = (int64_t)A.nx * A.ny;
+  const uint32_t cb = (uint32_t)(y * A.nx + x) * (uint32_t)sizeof(float);
+  const int64_t qstride = (int64_t)A.nzs * plane;
+  const T* w = cweights<T>(A);
+  T* out = reinterpret_cast<T*>(A.zbuf) + (int64_t)zl0 * plane + (int64_t)y * A.nx + x;
+#pragma unroll 1
+  for (int c = 0; c < 3; ++c) {
+    T acc[9][ZT];
+#pragma unroll
+    for (int q = 0; q < 9; ++q)
+#pragma unroll
+      for (int k = 0; k < ZT; ++k) acc[q][k] = (T)0;
+    // first window plane, made opaque per monomial group so that the plane offsets are
+    // recomputed (two scalar ops a plane) rather than held for all groups
+    int zz = wrapi(A.zs + zl0 - R, A.nz);
+    __asm__ volatile("" : "+s"(zz));
+    float in[kLook][4];  // planes in flight
+#pragma unroll
+    for (int j = 0; j < kLook; ++j) {
+      load_inputs(A, zz, cb, in[j]);
+      zz = zz + 1 == A.nz ? 0 : zz + 1;
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const T r = (T)in[j % kLook][0];
+      const T vx = (T)in[j % kLook][1], vy = (T)in[j % kLook][2], vz = (T)in[j % kLook][3];
+      if (j + kLook < NJ) {
+        load_inputs(A, zz, cb, in[j % kLook]);
+        zz = zz + 1 == A.nz ? 0 : zz + 1;
+      }
+      // keep the later loads below this point: the window is not held in registers
+      __builtin_amdgcn_sched_barrier(0);
+      T b0 = r;
+      if (c >= 1) b0 = b0 * vz;
+      if (c == 2) b0 = b0 * vz;
+      T p[9];  // p[a + 3 b] = rho u_z^c u_y^b u_x^a
+      T yb = b0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        if (b > 0) yb = yb * vy;
+        p[3 * b] = yb;
+        p[3 * b + 1] = yb * vx;
+        p[3 * b + 2] = p[3 * b + 1] * vx;
+      }
+#pragma unroll
+      for (int k = 0; k < ZT; ++k) {
+        const int t = j - k;  // tap of plane j for output k
+        if (t >= 0 && t <= 2 * R) {
+#pragma unroll
+          for (int q = 0; q < 9; ++q) acc[q][k] = fma(w[t], p[q], acc[q][k]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      T* o = out + (int64_t)(9 * c + q) * qstride;
+#pragma unroll
+      for (int k = 0; k < ZT; ++k)
+        if (k < nk) o[(int64_t)k * plane] = acc[q][k];
+    }
+  }
+}
+
+template <int R, typename T>
+struct CarrierLds {
+  static constexpr int HX = kTX + 2 * R;
+  static constexpr int HY = kTY + 2 * R;
+  static constexpr int HXP = HX | 1;  // odd row stride
+  static constexpr int NRAW = HX * HY;
+  static constexpr int QS = HY * HXP;
+  // monomials per LDS round: nine while they fit in 64 KiB, else three
+  static constexpr int G = 9 * QS * (int)sizeof(T) <= 65536 ? 9 : 3;
+  static constexpr int doubles = (G * QS * (int)sizeof(T) + 7) / 8;
+};
+
+// One direction of the Hermite synthesis, in place: coefficients (d_0, d_1, d_2) of P_0, P_1,
+// P_2 to the values at xh = -sqrt3, 0, +sqrt3, times the D1Q3 weights 1/6, 2/3, 1/6.
+template <typename T>
+__device__ __forceinline__ void synth1(T& v0, T& v1, T& v2) {
+  const T s = v0 + v2;
+  const T t = (T)1.7320508075688772 * v1;
+  const T mid = v0 - (T)0.5 * v2;
+  v0 = (s - t) * (T)(1.0 / 6.0);
+  v1 = mid * (T)(2.0 / 3.0);
+  v2 = (s + t) * (T)(1.0 / 6.0);
+}
+
+// d[a + 3 b + 9 c] = D_abc in, d[ix + 3 iy + 9 iz] = f of the population (ix - 1, iy - 1,
+// iz - 1) out: z, then y, then x.
+template <typename T>
+__device__ __forceinline__ void synth(T (&d)[27]) {
+#pragma unroll
+  for (int ab = 0; ab < 9; ++ab) synth1(d[ab], d[ab + 9], d[ab + 18]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int iz = 0; iz < 3; ++iz) synth1(d[a + 9 * iz], d[a + 3 + 9 * iz], d[a + 6 + 9 * iz]);
+#pragma unroll
+  for (int yz = 0; yz < 9; ++yz) synth1(d[3 * yz], d[3 * yz + 1], d[3 * yz + 2]);
+}
+
+template <int R, typename T>
+__global__ void __launch_bounds__(kXT) k_carrier_xy(CarrierArgs A) {
+  using L = CarrierLds<R, T>;
+  constexpr int HX = L::HX, HY = L::HY, HXP = L::HXP, QS = L::QS, G = L::G;
+  __shared__ double smem[L::doubles];
+  T* buf = reinterpret_cast<T*>(smem);
+  // item = (tile, run of kXZ planes); XCD bands: consecutive items (neighbouring tiles, which
+  // share halos) on one XCD
+  const int nzc = (A.nzs + kXZ - 1) / kXZ;
+  const int nb = A.ntiles * nzc;
+  const int per = (nb + 7) / 8;
+  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (item >= nb) return;
+  const int tile = item % A.ntiles, zc = item / A.ntiles;
+  const int x0 = (tile % A.ntx) * kTX, y0 = (tile / A.ntx) * kTY;
+  const int tid = threadIdx.x, px = tid % kTX, py = tid / kTX;
+  const int64_t plane = (int64_t)A.nx * A.ny;
+  const int64_t qstride = (int64_t)A.nzs * plane;
+  const T* w = cweights<T>(A);
+  const bool valid = x0 + px < A.nx && y0 + py < A.ny;
+  double acc[kCStat];  // this thread's FP64 sums over its points
+#pragma unroll
+  for (int k = 0; k < kCStat; ++k) acc[k] = 0.0;
+  const int z_hi = min((zc + 1) * kXZ, A.nzs);
+  for (int zl = zc * kXZ; zl < z_hi; ++zl) {
+    const T* zb = reinterpret_cast<const T*>(A.zbuf) + (int64_t)zl * plane;
+    T M[27];
+#pragma unroll
+    for (int g0 = 0; g0 < 27; g0 += G) {
+      for (int r = tid; r < L::NRAW; r += kXT) {
+        const int hx = r % HX, hy = r / HX;
+        const int64_t o = (int64_t)wrapi(y0 - R + hy, A.ny) * A.nx + wrapi(x0 - R + hx, A.nx);
+        T* d = buf + hy * HXP + hx;
+#pragma unroll
+        for (int q = 0; q < G; ++q) d[q * QS] = zb[(int64_t)(g0 + q) * qstride + o];
+      }
+      __syncthreads();
+      // x, in place: one (monomial, row) per task
+      for (int t = tid; t < G * HY; t += kXT) {
+        T* v = buf + t * HXP;
+        T vr[HX];
+#pragma unroll
+        for (int i = 0; i < HX; ++i) vr[i] = v[i];
+#pragma unroll
+        for (int o = 0; o < kTX; ++o) v[o] = tap_sum<R, T>(w, vr, o + R);
+      }
+      __syncthreads();
+      // y, in place: one (monomial, column) per task, outputs to rows 0 .. kTY - 1
+      for (int t = tid; t < G * kTX; t += kXT) {
+        T* v = buf + (t / kTX) * QS + t % kTX;
+        T vr[HY];
+#pragma unroll
+        for (int i = 0; i < HY; ++i) vr[i] = v[i * HXP];
+#pragma unroll
+        for (int o = 0; o < kTY; ++o) v[o * HXP] = tap_sum<R, T>(w, vr, o + R);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < G; ++q) M[g0 + q] = buf[q * QS + py * HXP + px];
+      __syncthreads();
+    }
+    // ---- Favre velocity and D_abc
+    const T rb = M[0];
+    const T ri = (T)1 / rb;
+    const T uv[3] = {M[1] * ri, M[3] * ri, M[9] * ri};
+    // D is a small difference of large filtered monomials and is formed in T; the Hermite
+    // synthesis that follows is a well-conditioned linear map and runs in FP32.
+    float D[27];
+    float herm[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // weighted energies of Hermite orders 2..6
+#pragma unroll
+    for (int m = 0; m < 27; ++m) {
+      if (mono_deg(m) <= 1) {
+        D[m] = 0.f;
+        continue;
+      }
+      T p = rb;
+      const int e[3] = {m % 3, (m / 3) % 3, m / 9};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (e[a] >= 1) p = p * uv[a];
+        if (e[a] >= 2) p = p * uv[a];
+      }
+      D[m] = (float)(M[m] - p);
+      herm[mono_deg(m) - 2] = fmaf((float)mono_norm(m) * D[m], D[m], herm[mono_deg(m) - 2]);
+    }
+    // tau = degree-2 D: xx xy xz yy yz zz
+    const float txx = D[2], txy = D[4], txz = D[10], tyy = D[6], tyz = D[12], tzz = D[18];
+    synth(D);
+    const int64_t g = (int64_t)(A.zs + zl) * plane + (int64_t)(y0 + py) * A.nx + x0 + px;
+    float sf2 = 0.f, serr = 0.f;
+    // population i = 9 (c_x + 1) + 3 (c_y + 1) + (c_z + 1)
+#pragma unroll
+    for (int ix = 0; ix < 3; ++ix) {
+#pragma unroll
+      for (int iy = 0; iy < 3; ++iy) {
+#pragma unroll
+        for (int iz = 0; iz < 3; ++iz) {
+          const int cx = ix - 1, cy = iy - 1, cz = iz - 1;
+          // f_h2 = w_i (sum_a P_2(xh_a) tau_aa + sum_{a<b} xh_a xh_b tau_ab),
+          // xh_a xh_b = 3 c_a c_b
+          float h = (cx ? 1.f : -0.5f) * txx + (cy ? 1.f : -0.5f) * tyy +
+                    (cz ? 1.f : -0.5f) * tzz;
+          if (cx && cy) h += (float)(3 * cx * cy) * txy;
+          if (cx && cz) h += (float)(3 * cx * cz) * txz;
+          if (cy && cz) h += (float)(3 * cy * cz) * tyz;
+          const float wi = (float)((cx ? 1.0 / 6.0 : 2.0 / 3.0) * (cy ? 1.0 / 6.0 : 2.0 / 3.0) *
+                                   (cz ? 1.0 / 6.0 : 2.0 / 3.0));
+          const float fh = wi * h;
+          const float fs = D[ix + 3 * iy + 9 * iz];
+          const int i = 9 * ix + 3 * iy + iz;
+          if (valid) {
+            if (A.f_sgs) A.f_sgs[(int64_t)i * A.ntot + g] = fs;
+            if (A.f_h2) A.f_h2[(int64_t)i * A.ntot + g] = fh;
+          }
+          const float e = fs - fh;
+          sf2 = fmaf(fs, fs, sf2);
+          serr = fmaf(e, e, serr);
+        }
+      }
+    }
+    // the point's sums (FP32 over its 27 populations) join the FP64 accumulators
+    const bool finite = isfinite(sf2 + serr + herm[0] + herm[1] + herm[2] + herm[3] + herm[4]);
+    const bool use = valid && finite;
+    acc[C_N] += use ? 1.0 : 0.0;
+    acc[C_F2] += use ? (double)sf2 : 0.0;
+    acc[C_ERR2] += use ? (double)serr : 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) acc[C_HERM + k] += use ? (double)herm[k] : 0.0;
+    acc[C_NONFINITE] += valid && !finite ? 1.0 : 0.0;
+  }
+  if (!A.partials) return;
+  // ---- fixed-order wave and block reduction, one record per workgroup
+#pragma unroll
+  for (int k = 0; k < kCStat; ++k) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc[k] += __shfl_xor(acc[k], d);
+  }
+  if (__lane_id() == 0) {
+#pragma unroll
+    for (int k = 0; k < kCStat; ++k) smem[(tid >> 6) * kCStat + k] = acc[k];
+  }
+  __syncthreads();
+  if (tid < kCStat) {
+    double a = 0;
+#pragma unroll
+    for (int wv = 0; wv < kXT / 64; ++wv) a += smem[wv * kCStat + tid];
+    A.partials[(int64_t)item * kCStat + tid] = a;
+  }
+}
+
+template <int R>
+hipError_t launch_z_of(const CarrierArgs& a, int fp64, hipStream_t s) {
+  const int zt = fp64 ? cz_planes<double>() : cz_planes<float>();
+  const dim3 grid((a.nx + kZB - 1) / kZB, a.ny, (a.nzs + zt - 1) / zt);
+  if (fp64)
+    hipLaunchKernelGGL((k_carrier_z<R, double>), grid, dim3(kZB), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_carrier_z<R, float>), grid, dim3(kZB), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_xy_of(const CarrierArgs& a, int fp64, hipStream_t s) {
+  const int64_t nb = carrier_xy_records(a);
+  const dim3 grid((unsigned)(8 * ((nb + 7) / 8)));
+  if (fp64)
+    hipLaunchKernelGGL((k_carrier_xy<R, double>), grid, dim3(kXT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_carrier_xy<R, float>), grid, dim3(kXT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <template <int> class F, typename... Args>
+hipError_t dispatch_r(int R, Args... args) {
+  switch (R) {
+    case 1: return F<1>::run(args...);
+    case 2: return F<2>::run(args...);
+    case 3: return F<3>::run(args...);
+    case 4: return F<4>::run(args...);
+    case 5: return F<5>::run(args...);
+    case 6: return F<6>::run(args...);
+    case 7: return F<7>::run(args...);
+    case 8: return F<8>::run(args...);
+    case 9: return F<9>::run(args...);
+    case 10: return F<10>::run(args...);
+    case 11: return F<11>::run(args...);
+    case 12: return F<12>::run(args...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int R>
+struct RunZ {
+  static hipError_t run(const CarrierArgs& a, int fp64, hipStream_t s) { return launch_z_of<R>(a, fp64, s); }
+};
+template <int R>
+struct RunXY {
+  static hipError_t run(const CarrierArgs& a, int fp64, hipStream_t s) { return launch_xy_of<R>(a, fp64, s); }
+};
+
+}  // namespace
+
+int carrier_tile_x() { return kTX; }
+int carrier_tile_y() { return kTY; }
+int64_t carrier_xy_records(const CarrierArgs& a) {
+  return (int64_t)a.ntiles * ((a.nzs + kXZ - 1) / kXZ);
+}
+int carrier_z_planes(int fp64) { return fp64 ? cz_planes<double>() : cz_planes<float>(); }
+
+hipError_t launch_carrier_z(const CarrierArgs& a, int R, int fp64, hipStream_t s) {
+  if (a.ny > 65535) return hipErrorInvalidValue;
+  return dispatch_r<RunZ>(R, a, fp64, s);
+}
+
+hipError_t launch_carrier_xy(const CarrierArgs& a, int R, int fp64, hipStream_t s) {
+  return dispatch_r<RunXY>(R, a, fp64, s);
+}
+
+}  // namespace kcf

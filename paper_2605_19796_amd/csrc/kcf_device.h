@@ -12,6 +12,15 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// sum_m w_m v[c + m], m = -R..R, with w symmetric: w_0 v_c + sum_{m>0} w_m (v_{c+m} + v_{c-m}).
+template <int R, typename T>
+__device__ __forceinline__ T tap_sum(const T* w, const T* v, int c) {
+  T s = w[R] * v[c];
+#pragma unroll
+  for (int m = 1; m <= R; ++m) s = fma(w[R + m], v[c + m] + v[c - m], s);
+  return s;
+}
+
 // ---------------------------------------------------------------- per-point closures + stats
 struct PointOut {
   float G[3][3];

@@ -103,6 +103,31 @@ int taps_tile_y();
 int taps_z_planes(int fp64);
 hipError_t launch_taps(const TapArgs& a, int R, int fp64, hipStream_t s);
 
+// SGS carrier of the D3Q27 lattice (kcf_carrier.hip)
+constexpr int kCStat = 9;  // FP64 sums of the carrier
+enum CarrierSlot { C_N = 0, C_F2 = 1, C_ERR2 = 2, C_HERM = 3, C_NONFINITE = 8 };
+
+struct CarrierArgs {
+  const float* rho;
+  const float* u;
+  int nx, ny, nz;
+  int64_t ntot;
+  int ntx, nty, ntiles;    // output tiles of the x-y pass
+  int zs, nzs;             // z slab: planes zs .. zs + nzs - 1
+  void* zbuf;              // z-filtered monomials [27][nzs][ny][nx], float or double
+  float w[kMaxTaps];       // taps w_{-R..R}
+  double wd[kMaxTaps];
+  float* f_sgs;            // [27][N], or NULL
+  float* f_h2;             // [27][N], or NULL
+  double* partials;        // [carrier_xy_records][kCStat] records of the slab, or NULL
+};
+int carrier_tile_x();               // the x-y tile
+int carrier_tile_y();
+int64_t carrier_xy_records(const CarrierArgs& a);  // statistics records of one slab
+int carrier_z_planes(int fp64);     // planes per thread of the z pass
+hipError_t launch_carrier_z(const CarrierArgs& a, int R, int fp64, hipStream_t s);
+hipError_t launch_carrier_xy(const CarrierArgs& a, int R, int fp64, hipStream_t s);
+
 // box kernels (kcf_box.hip)
 struct BoxGeom {
   int tile_x, tile_y;  // output columns of a tile

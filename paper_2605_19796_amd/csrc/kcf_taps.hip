@@ -41,15 +41,6 @@ __device__ __forceinline__ const float* tap_weights<float>(const TapArgs& A) { r
 template <>
 __device__ __forceinline__ const double* tap_weights<double>(const TapArgs& A) { return A.wd; }
 
-// sum_m w_m v[c + m], m = -R..R, with w symmetric: w_0 v_c + sum_{m>0} w_m (v_{c+m} + v_{c-m}).
-template <int R, typename T>
-__device__ __forceinline__ T tap_sum(const T* w, const T* v, int c) {
-  T s = w[R] * v[c];
-#pragma unroll
-  for (int m = 1; m <= R; ++m) s = fma(w[R + m], v[c + m] + v[c - m], s);
-  return s;
-}
-
 template <int R, typename T>
 __global__ void __launch_bounds__(kTT) k_taps_xy(TapArgs A) {
   using L = TapLds<R, T>;

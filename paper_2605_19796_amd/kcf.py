@@ -57,6 +57,14 @@ class WidthStats(C.Structure):
         return d
 
 
+class CarrierStats(C.Structure):
+    _fields_ = [("sgs_l2", C.c_double), ("err_l2", C.c_double), ("rel_err", C.c_double),
+                ("hermite", C.c_double * 5), ("n_points", C.c_int64), ("n_nonfinite", C.c_int64),
+                ("raw", C.c_double * 9)]
+
+    as_dict = WidthStats.as_dict
+
+
 class InputSummary(C.Structure):
     _fields_ = [("mean_rho", C.c_double), ("ek", C.c_double), ("enstrophy", C.c_double),
                 ("n_nonfinite", C.c_int64)]
@@ -81,6 +89,8 @@ _SIGS = {
     "kcf_grad_closure": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_double, C.c_double, C.POINTER(ClosureParams),
                                    C.POINTER(Outputs), C.POINTER(WidthStats)]),
+    "kcf_sgs_carrier": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.POINTER(Filter), C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(CarrierStats)]),
     "kcf_input_stats": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p,
                                   C.POINTER(InputSummary)]),
     "kcf_reduce_check": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -252,6 +262,17 @@ class Context:
         check(self._lib.kcf_grad_closure(self.handle, C.byref(g), _ptr(rho_bar), _ptr(ut), _ptr(tau),
                                          delta, m2, C.byref(cp) if cp is not None else None,
                                          C.byref(o), C.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def sgs_carrier(self, rho, u, h, filt, f_sgs=None, f_h2=None, stats=True):
+        """D3Q27 SGS carrier of one filter (kind, n[, precision]): f_sgs and f_h2 are optional
+        (27, nz, ny, nx) device float32 tensors; returns the statistics dict or None."""
+        nz, ny, nx = rho.shape
+        g = Grid(nx, ny, nz, h)
+        fl = Filter(*filt) if len(filt) == 3 else Filter(filt[0], filt[1], 0)
+        st = CarrierStats() if stats else None
+        check(self._lib.kcf_sgs_carrier(self.handle, C.byref(g), C.byref(fl), _ptr(rho), _ptr(u),
+                                        _ptr(f_sgs), _ptr(f_h2), C.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
     def input_stats(self, rho, u, h):
