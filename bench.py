@@ -1,6 +1,7 @@
 """Throughput of the filtering path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-learned]
+                    [--no-carrier]
 
 Workload: 512^3 periodic grid of synthetic spectral turbulence (u_rms 0.3, k0 16,
 rho = 1 + 0.2 s), FP32 fields resident in HBM; one step = four box-filter widths (2h, 4h,
@@ -14,6 +15,10 @@ Prints one JSON line. `value` is grid points per second (each point filtered at 
 widths). `roofline` is for the kernel with the largest share of the step: algorithmic bytes
 of one launch (inputs 16 B + outputs 40 B per point) over its average HIP-event time on the
 stream it runs on.
+
+Further sections of the same line: `carrier`, the a priori D3Q27 SGS carrier (f_sgs and its
+second-order Hermite reconstruction, stored, with statistics) on the 512^3 field at box 4h
+and 8h and on the 256^3 Gaussian-8h field; `learned`, training and the learned-vs-plain race.
 
 Profiling modes (for rocprofv3 runs): --profile-run times a few steps and skips the CPU
 baseline and the learned section; --copy-calibration runs only a plain device copy of known
@@ -176,6 +181,55 @@ def learned_section(ctx, args):
     return out
 
 
+CARRIER_BYTES_PER_POINT = 16 + 2 * 27 * 4  # read rho, u; write f_sgs and f_h2 (27 each)
+
+
+def carrier_section(ctx, rho, u, args):
+    """A priori D3Q27 SGS carrier (f_sgs, its second-order Hermite reconstruction f_h2, both
+    stored, and their statistics) on the 512^3 field at box 4h (FP64 sums) and 8h (FP32),
+    and on the 256^3 Gaussian-8h field."""
+    import torch
+    from paper_2605_19796_amd import kcf, synth
+    out = {}
+    cases = [("box4h_512", rho, u, (kcf.BOX, 4)), ("box8h_512", rho, u, (kcf.BOX, 8))]
+    r2, u2 = synth.workload_fields("c256_gauss8", device=rho.device)
+    cases.append(("gauss8h_256", r2, u2, (kcf.GAUSS, 8)))
+    reps = 2 if args.profile_run else 5
+    for name, r, v, filt in cases:
+        n = r.shape[0]
+        h = 2 * math.pi / n
+        fs = torch.empty((27,) + tuple(r.shape), dtype=torch.float32, device=r.device)
+        fh = torch.empty_like(fs)
+        progress(f"carrier {name}")
+        st = ctx.sgs_carrier(r, v, h, filt, fs, fh)  # warm-up (allocates the slab buffer)
+        ctx.enable_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = ctx.sgs_carrier(r, v, h, filt, fs, fh)
+        t1 = time.perf_counter()
+        kt = ctx.kernel_times()
+        ctx.enable_timing(False)
+        ms = (t1 - t0) * 1e3 / reps
+        kz, kxy = sum(kt[0::2]) / reps, sum(kt[1::2]) / reps
+        pts = float(n) ** 3
+        gbs = CARRIER_BYTES_PER_POINT * pts / ((kz + kxy) * 1e-3) / 1e9
+        out[name] = {
+            "grid": n, "filter": ["box", "gauss"][filt[0]], "width_h": filt[1],
+            "sums": "f64" if filt[1] <= 4 else "f32",
+            "ms_per_call": ms, "points_per_s": pts / (ms * 1e-3),
+            "kernel_ms": {"k_carrier_z": kz, "k_carrier_xy": kxy},
+            "bytes_per_point": CARRIER_BYTES_PER_POINT,
+            "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "rel_err_h2": st["rel_err"], "sgs_l2": st["sgs_l2"], "hermite_2_to_6": st["hermite"],
+        }
+        del fs, fh
+        torch.cuda.empty_cache()
+    del r2, u2
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration():
     """One plain device-to-device copy of COPY_BYTES, for scaling FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -196,6 +250,7 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-carrier", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
                     help="a few steps only (no CPU baseline, no learned section)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -292,6 +347,9 @@ def main():
         progress("cpu baseline (oracle)")
         line["cpu_baseline"] = cpu_baseline(rho, u)
     del outs
+    torch.cuda.empty_cache()
+    if not args.no_carrier:
+        line["carrier"] = carrier_section(ctx, rho, u, args)
     if not args.no_learned:
         del rho, u
         torch.cuda.empty_cache()

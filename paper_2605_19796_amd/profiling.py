@@ -3,6 +3,9 @@
     python -m paper_2605_19796_amd.profiling kernel-stats DIR OUT.txt --command "..."
     python -m paper_2605_19796_amd.profiling traffic --kernel NAME --fetch DIR --write DIR \\
         --calib-fetch DIR --calib-write DIR --out OUT.json --commands "..." "..."
+    python -m paper_2605_19796_amd.profiling traffic-per-call --kernel NAME [NAME ...] \\
+        --calls C --points P --workload "..." --fetch DIR --write DIR --calib-fetch DIR \\
+        --calib-write DIR --out OUT.json --commands "..." "..."
 
 kernel-stats: the per-kernel table of a `rocprofv3 --kernel-trace --stats` run (calls, total
 and average duration), as text.
@@ -108,6 +111,28 @@ def traffic(args):
     print(json.dumps(res, indent=1))
 
 
+def traffic_per_call(args):
+    """HBM bytes of one call of a multi-launch entry point: each kernel's FETCH_SIZE and
+    WRITE_SIZE summed over its dispatches, divided by the number of calls, copy-calibrated."""
+    sys.path.insert(0, ROOT)
+    import bench
+    cf, _ = _largest(args.calib_fetch, "FETCH_SIZE")
+    cw, _ = _largest(args.calib_write, "WRITE_SIZE")
+    kf, kw = bench.COPY_BYTES / cf, bench.COPY_BYTES / cw
+    res = {"workload": args.workload, "calls": args.calls, "points": args.points,
+           "bytes_per_fetch_unit": kf, "bytes_per_write_unit": kw, "kernels": {},
+           "commands": args.commands}
+    for k in args.kernel:
+        f = _counter(args.fetch, "FETCH_SIZE", k)
+        w = _counter(args.write, "WRITE_SIZE", k)
+        fb, wb = sum(f) * kf / args.calls, sum(w) * kw / args.calls
+        res["kernels"][k] = {"dispatches": len(f), "fetch_bytes_per_call": fb,
+                             "write_bytes_per_call": wb,
+                             "bytes_per_point": (fb + wb) / args.points}
+    json.dump(res, open(args.out, "w"), indent=1)
+    print(json.dumps(res, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -121,11 +146,20 @@ def main():
     b.add_argument("--commands", nargs="+", required=True)
     b.add_argument("--rdreq", default=None, help="run with the read-request size counters")
     b.add_argument("--cal-rdreq", default=None, dest="cal_rdreq")
+    c = sub.add_parser("traffic-per-call")
+    for k in ("fetch", "write", "calib_fetch", "calib_write", "out", "workload"):
+        c.add_argument("--" + k.replace("_", "-"), required=True, dest=k)
+    c.add_argument("--kernel", nargs="+", required=True)
+    c.add_argument("--calls", type=int, required=True)
+    c.add_argument("--points", type=float, required=True)
+    c.add_argument("--commands", nargs="+", required=True)
     args = ap.parse_args()
     if args.cmd == "kernel-stats":
         kernel_stats(args.dir, args.out, args.command)
-    else:
+    elif args.cmd == "traffic":
         traffic(args)
+    else:
+        traffic_per_call(args)
 
 
 if __name__ == "__main__":
