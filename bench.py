@@ -18,7 +18,9 @@ stream it runs on.
 
 Further sections of the same line: `carrier`, the a priori D3Q27 SGS carrier (f_sgs and its
 second-order Hermite reconstruction, stored, with statistics) on the 512^3 field at box 4h
-and 8h and on the 256^3 Gaussian-8h field; `learned`, training and the learned-vs-plain race.
+and 8h and on the 256^3 Gaussian-8h field; `moment3`, the third-order SGS moment and the
+Favre temperature on the 512^3 field with a spectral temperature; `learned`, training and the
+learned-vs-plain race.
 
 Profiling modes (for rocprofv3 runs): --profile-run times a few steps and skips the CPU
 baseline and the learned section; --copy-calibration runs only a plain device copy of known
@@ -230,6 +232,49 @@ def carrier_section(ctx, rho, u, args):
     return out
 
 
+MOMENT3_BYTES_PER_POINT = 20 + 11 * 4  # read rho, u, theta; write m3 (10) and theta_t
+
+
+def moment3_section(ctx, rho, u, args):
+    """Third-order SGS moment and Favre temperature (both stored, with statistics) on the
+    512^3 field with a spectral temperature, box 4h (FP64 sums) and 8h (FP32)."""
+    import torch
+    from paper_2605_19796_amd import kcf, synth
+    n = rho.shape[0]
+    h = 2 * math.pi / n
+    theta = synth.workload_temperature("c512_box_multi", device=rho.device, n=n)
+    m3 = torch.empty((10,) + tuple(rho.shape), dtype=torch.float32, device=rho.device)
+    tt = torch.empty_like(rho)
+    out = {}
+    reps = 2 if args.profile_run else 5
+    for name, filt in (("box4h_512", (kcf.BOX, 4)), ("box8h_512", (kcf.BOX, 8))):
+        progress(f"moment3 {name}")
+        st = ctx.sgs_moment3(rho, u, h, filt, theta, m3, tt)
+        ctx.enable_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = ctx.sgs_moment3(rho, u, h, filt, theta, m3, tt)
+        t1 = time.perf_counter()
+        kt = ctx.kernel_times()
+        ctx.enable_timing(False)
+        ms = (t1 - t0) * 1e3 / reps
+        kz, kxy = sum(kt[0::2]) / reps, sum(kt[1::2]) / reps
+        pts = float(n) ** 3
+        gbs = MOMENT3_BYTES_PER_POINT * pts / ((kz + kxy) * 1e-3) / 1e9
+        out[name] = {
+            "grid": n, "width_h": filt[1], "sums": "f64" if filt[1] <= 4 else "f32",
+            "ms_per_call": ms, "points_per_s": pts / (ms * 1e-3),
+            "kernel_ms": {"k_moment3_z": kz, "k_moment3_xy": kxy},
+            "bytes_per_point": MOMENT3_BYTES_PER_POINT,
+            "achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+            "rms_m3": st["rms_m3"], "mean_theta_t": st["mean_theta_t"],
+        }
+    del theta, m3, tt
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration():
     """One plain device-to-device copy of COPY_BYTES, for scaling FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -250,7 +295,8 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
-    ap.add_argument("--no-carrier", action="store_true")
+    ap.add_argument("--no-carrier", action="store_true",
+                    help="skip the carrier and third-order moment sections")
     ap.add_argument("--profile-run", action="store_true",
                     help="a few steps only (no CPU baseline, no learned section)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -350,6 +396,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_carrier:
         line["carrier"] = carrier_section(ctx, rho, u, args)
+        line["moment3"] = moment3_section(ctx, rho, u, args)
     if not args.no_learned:
         del rho, u
         torch.cuda.empty_cache()

@@ -120,6 +120,18 @@ typedef struct {
                                    E_2..E_6, non-finite count */
 } kcf_carrier_stats;
 
+/* Statistics of the third-order SGS moment (kcf_sgs_moment3), over the finite points; the
+ * components in the order xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz. */
+typedef struct {
+  double mean_m3[10];           /* <m3_c> */
+  double rms_m3[10];            /* sqrt(<m3_c^2>) */
+  double mean_theta_t;          /* <theta_t> (1 without a temperature field) */
+  int64_t n_points;             /* points counted (finite outputs) */
+  int64_t n_nonfinite;          /* points with a non-finite output (excluded from sums) */
+  double raw[23];               /* count, sums of m3_c, sums of m3_c^2, sum of theta_t,
+                                   non-finite count */
+} kcf_moment3_stats;
+
 typedef struct {
   double mean_rho;              /* <rho> */
   double ek;                    /* <rho |u|^2 / 2> */
@@ -205,6 +217,25 @@ int kcf_grad_closure(kcf_ctx *ctx, const kcf_grid *grid, const float *rho_bar, c
 int kcf_sgs_carrier(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filter,
                     const float *rho, const float *u, float *f_sgs, float *f_h2,
                     kcf_carrier_stats *stats);
+
+/* Third-order SGS moment and Favre temperature for one filter width:
+ *   m3_ijk  = bar(rho u_i u_j u_k) - rho_bar ut_i ut_j ut_k   (10 components, device [10][N],
+ *             order xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz),
+ * the coefficient of the third-order Hermite term of the carrier's series (Sec. "Filtered
+ * nondimensional recorrelated BGK-BE", eq. f_sgs_hermite; with the same velocity units as
+ * kcf_sgs_carrier), and
+ *   theta_t = bar(rho theta) / rho_bar                        (device [N]),
+ * the Favre temperature (definition after eq. f0resolved). theta (device [N]) may be NULL
+ * (isothermal: then theta_t must be NULL and its statistic is 1). m3, theta_t and stats (host)
+ * may each be NULL, but not all three. filter->precision as for kcf_filter_favre. The call
+ * filters 14 quantities (15 with theta) in z slabs through a context buffer of at most
+ * 8 GiB, two timed kernels per slab; with stats it synchronises.
+ * Errors: KCF_EINVAL for null rho/u/grid/filter, nothing requested, theta_t without theta,
+ * bad filter or n < 3; KCF_EUNSUPPORTED when 2R+1 exceeds a grid dimension, R > 12 or
+ * ny > 65535; KCF_ENOMEM when a context buffer cannot be allocated. */
+int kcf_sgs_moment3(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filter,
+                    const float *rho, const float *u, const float *theta, float *m3,
+                    float *theta_t, kcf_moment3_stats *stats);
 
 /* E_k, enstrophy and <rho> of the unfiltered input (synchronises). */
 int kcf_input_stats(kcf_ctx *ctx, const kcf_grid *grid, const float *rho, const float *u,

@@ -231,6 +231,80 @@ int choose_zchunks(int64_t items_per_chunk, int nz, int R, int blocks_per_cu) {
   return best_n;
 }
 
+// The two passes of the monomial filters (kcf_monomials.hip) over z slabs whose filtered
+// quantities fit the context buffer; FP64 statistics records reduced into c->d_sums when
+// `stats` is set.
+int run_monomials(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, int set, int nq,
+                  int nstat, MonoArgs& A, bool stats) {
+  Taps taps;
+  int rc = compute_taps(filter->kind, filter->delta_over_h, grid->h, taps);
+  if (rc) return rc;
+  const int R = taps.R;
+  if (R > kMaxR) return fail(KCF_EUNSUPPORTED, "filter radius above 12 cells");
+  if (2 * R + 1 > std::min(grid->nx, std::min(grid->ny, grid->nz)))
+    return fail(KCF_EUNSUPPORTED, "filter support 2R+1 exceeds the grid");
+  const int p = filter->precision;
+  if (p < 0 || p > 2) return fail(KCF_EINVAL, "precision must be 0 (auto), 1 (fp32) or 2 (fp64)");
+  const int fp64 = p == 2 || (p == 0 && filter->delta_over_h <= 4);
+  if (grid->ny > 65535) return fail(KCF_EUNSUPPORTED, "ny above 65535");
+  KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  A.nx = grid->nx;
+  A.ny = grid->ny;
+  A.nz = grid->nz;
+  A.ntot = (int64_t)grid->nx * grid->ny * grid->nz;
+  A.ntx = (grid->nx + mono_tile_x() - 1) / mono_tile_x();
+  A.nty = (grid->ny + mono_tile_y() - 1) / mono_tile_y();
+  A.ntiles = A.ntx * A.nty;
+  A.nq = nq;
+  for (int m = 0; m < 2 * R + 1; ++m) {
+    A.wd[m] = taps.wd[m];
+    A.w[m] = (float)taps.wd[m];
+  }
+  // z slabs whose filtered quantities fit the buffer cap (the whole field if they can)
+  const int64_t plane = (int64_t)grid->nx * grid->ny;
+  const size_t per_plane = (size_t)nq * plane * (fp64 ? sizeof(double) : sizeof(float));
+  const int zt = mono_z_planes(fp64);
+  int slab = grid->nz;
+  if (per_plane * (size_t)grid->nz > kTapBufferCap)
+    slab = std::max(zt, (int)(kTapBufferCap / per_plane) / zt * zt);
+  if ((rc = ensure_buffer(c, c->d_xy, c->xy_cap, per_plane * (size_t)slab,
+                          "cannot allocate the monomial slab buffer")))
+    return rc;
+  A.zbuf = c->d_xy;
+  int64_t nrec = 0;  // statistics records of all slabs
+  for (int zs = 0; zs < grid->nz; zs += slab) {
+    A.nzs = std::min(slab, grid->nz - zs);
+    nrec += mono_xy_records(A);
+  }
+  if (stats) {
+    if (nrec > INT32_MAX) return fail(KCF_EUNSUPPORTED, "grid too large for statistics");
+    if ((rc = ensure_partials(c, (size_t)nrec * nstat))) return rc;
+  }
+  int64_t rec0 = 0;
+  for (int zs = 0; zs < grid->nz; zs += slab) {
+    A.zs = zs;
+    A.nzs = std::min(slab, grid->nz - zs);
+    A.partials = stats ? c->d_part + (size_t)rec0 * nstat : nullptr;
+    rec0 += mono_xy_records(A);
+    if ((rc = timed_begin(c))) return rc;
+    hipError_t e = launch_mono_z(A, set, R, fp64, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "z pass launch");
+    if ((rc = timed_end(c))) return rc;
+    if ((rc = timed_begin(c))) return rc;
+    e = launch_mono_xy(A, set, R, fp64, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "x-y pass launch");
+    if ((rc = timed_end(c))) return rc;
+  }
+  if (stats) {
+    hipError_t e = launch_reduce(c->d_part, (int)nrec, nstat, c->d_sums, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * nstat, hipMemcpyDeviceToHost,
+                           c->stream), "stats copy");
+    KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+  }
+  return KCF_OK;
+}
+
 }  // namespace
 
 namespace kcf {
@@ -521,75 +595,15 @@ int kcf_sgs_carrier(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, 
   if (rc) return rc;
   if (!filter || !rho || !u) return fail(KCF_EINVAL, "NULL argument");
   if (!f_sgs && !f_h2 && !stats) return fail(KCF_EINVAL, "nothing requested");
-  Taps taps;
-  if ((rc = compute_taps(filter->kind, filter->delta_over_h, grid->h, taps))) return rc;
-  const int R = taps.R;
-  if (R > kMaxR) return fail(KCF_EUNSUPPORTED, "filter radius above 12 cells");
-  if (2 * R + 1 > std::min(grid->nx, std::min(grid->ny, grid->nz)))
-    return fail(KCF_EUNSUPPORTED, "filter support 2R+1 exceeds the grid");
-  const int p = filter->precision;
-  if (p < 0 || p > 2) return fail(KCF_EINVAL, "precision must be 0 (auto), 1 (fp32) or 2 (fp64)");
-  const int fp64 = p == 2 || (p == 0 && filter->delta_over_h <= 4);
-  if (grid->ny > 65535) return fail(KCF_EUNSUPPORTED, "ny above 65535");
-  KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
-  CarrierArgs A;
+  MonoArgs A;
   std::memset(&A, 0, sizeof(A));
   A.rho = rho;
   A.u = u;
-  A.nx = grid->nx;
-  A.ny = grid->ny;
-  A.nz = grid->nz;
-  A.ntot = (int64_t)grid->nx * grid->ny * grid->nz;
-  A.ntx = (grid->nx + carrier_tile_x() - 1) / carrier_tile_x();
-  A.nty = (grid->ny + carrier_tile_y() - 1) / carrier_tile_y();
-  A.ntiles = A.ntx * A.nty;
-  for (int m = 0; m < 2 * R + 1; ++m) {
-    A.wd[m] = taps.wd[m];
-    A.w[m] = (float)taps.wd[m];
-  }
   A.f_sgs = f_sgs;
   A.f_h2 = f_h2;
-  // z slabs whose 27 filtered monomials fit the buffer cap (the whole field if they can)
-  const int64_t plane = (int64_t)grid->nx * grid->ny;
-  const size_t per_plane = 27 * (size_t)plane * (fp64 ? sizeof(double) : sizeof(float));
-  const int zt = carrier_z_planes(fp64);
-  int slab = grid->nz;
-  if (per_plane * (size_t)grid->nz > kTapBufferCap)
-    slab = std::max(zt, (int)(kTapBufferCap / per_plane) / zt * zt);
-  if ((rc = ensure_buffer(c, c->d_xy, c->xy_cap, per_plane * (size_t)slab,
-                          "cannot allocate the carrier slab buffer")))
+  if ((rc = run_monomials(c, grid, filter, kSetCarrier, 27, kCStat, A, stats != nullptr)))
     return rc;
-  A.zbuf = c->d_xy;
-  int64_t nrec = 0;  // statistics records of all slabs
-  for (int zs = 0; zs < grid->nz; zs += slab) {
-    A.nzs = std::min(slab, grid->nz - zs);
-    nrec += carrier_xy_records(A);
-  }
   if (stats) {
-    if (nrec > INT32_MAX) return fail(KCF_EUNSUPPORTED, "grid too large for statistics");
-    if ((rc = ensure_partials(c, (size_t)nrec * kCStat))) return rc;
-  }
-  int64_t rec0 = 0;
-  for (int zs = 0; zs < grid->nz; zs += slab) {
-    A.zs = zs;
-    A.nzs = std::min(slab, grid->nz - zs);
-    A.partials = stats ? c->d_part + (size_t)rec0 * kCStat : nullptr;
-    rec0 += carrier_xy_records(A);
-    if ((rc = timed_begin(c))) return rc;
-    hipError_t e = launch_carrier_z(A, R, fp64, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "carrier z launch");
-    if ((rc = timed_end(c))) return rc;
-    if ((rc = timed_begin(c))) return rc;
-    e = launch_carrier_xy(A, R, fp64, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "carrier x-y launch");
-    if ((rc = timed_end(c))) return rc;
-  }
-  if (stats) {
-    hipError_t e = launch_reduce(c->d_part, (int)nrec, kCStat, c->d_sums, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "reduce launch");
-    KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * kCStat, hipMemcpyDeviceToHost,
-                           c->stream), "stats copy");
-    KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     const double* raw = c->h_sums;
     std::memset(stats, 0, sizeof(*stats));
     std::memcpy(stats->raw, raw, sizeof(double) * kCStat);
@@ -601,6 +615,43 @@ int kcf_sgs_carrier(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, 
       stats->err_l2 = raw[C_ERR2] / n;
       stats->rel_err = raw[C_F2] > 0 ? std::sqrt(raw[C_ERR2] / raw[C_F2]) : 0.0;
       for (int k = 0; k < 5; ++k) stats->hermite[k] = raw[C_HERM + k] / n;
+    }
+  }
+  return KCF_OK;
+}
+
+int kcf_sgs_moment3(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, const float* rho,
+                    const float* u, const float* theta, float* m3, float* theta_t,
+                    kcf_moment3_stats* stats) {
+  if (!c) return fail(KCF_EINVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!filter || !rho || !u) return fail(KCF_EINVAL, "NULL argument");
+  if (!m3 && !theta_t && !stats) return fail(KCF_EINVAL, "nothing requested");
+  if (theta_t && !theta) return fail(KCF_EINVAL, "theta_t needs a temperature field");
+  MonoArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.rho = rho;
+  A.u = u;
+  A.theta = theta;
+  A.m3 = m3;
+  A.theta_t = theta_t;
+  if ((rc = run_monomials(c, grid, filter, kSetMoment3, theta ? 15 : 14, kM3Stat, A,
+                          stats != nullptr)))
+    return rc;
+  if (stats) {
+    const double* raw = c->h_sums;
+    std::memset(stats, 0, sizeof(*stats));
+    std::memcpy(stats->raw, raw, sizeof(double) * kM3Stat);
+    const double n = raw[M3_N];
+    stats->n_points = (int64_t)llround(n);
+    stats->n_nonfinite = (int64_t)llround(raw[M3_NONFINITE]);
+    if (n > 0) {
+      for (int k = 0; k < 10; ++k) {
+        stats->mean_m3[k] = raw[M3_SUM + k] / n;
+        stats->rms_m3[k] = std::sqrt(raw[M3_SQ + k] / n);
+      }
+      stats->mean_theta_t = raw[M3_THETA] / n;
     }
   }
   return KCF_OK;

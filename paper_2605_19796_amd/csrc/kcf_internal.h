@@ -103,30 +103,38 @@ int taps_tile_y();
 int taps_z_planes(int fp64);
 hipError_t launch_taps(const TapArgs& a, int R, int fp64, hipStream_t s);
 
-// SGS carrier of the D3Q27 lattice (kcf_carrier.hip)
-constexpr int kCStat = 9;  // FP64 sums of the carrier
+// Filtered monomials of rho u (and rho theta): the SGS carrier of the D3Q27 lattice and the
+// third-order SGS moment (kcf_monomials.hip)
+constexpr int kSetCarrier = 0, kSetMoment3 = 1;
+constexpr int kCStat = 9;   // FP64 sums of the carrier
 enum CarrierSlot { C_N = 0, C_F2 = 1, C_ERR2 = 2, C_HERM = 3, C_NONFINITE = 8 };
+constexpr int kM3Stat = 23;  // FP64 sums of the third-order moment
+enum Moment3Slot { M3_N = 0, M3_SUM = 1, M3_SQ = 11, M3_THETA = 21, M3_NONFINITE = 22 };
 
-struct CarrierArgs {
+struct MonoArgs {
   const float* rho;
   const float* u;
+  const float* theta;      // temperature (third-order set only), or NULL
   int nx, ny, nz;
   int64_t ntot;
   int ntx, nty, ntiles;    // output tiles of the x-y pass
   int zs, nzs;             // z slab: planes zs .. zs + nzs - 1
-  void* zbuf;              // z-filtered monomials [27][nzs][ny][nx], float or double
+  int nq;                  // quantities kept in the slab buffer
+  void* zbuf;              // z-filtered quantities [nq][nzs][ny][nx], float or double
   float w[kMaxTaps];       // taps w_{-R..R}
   double wd[kMaxTaps];
-  float* f_sgs;            // [27][N], or NULL
-  float* f_h2;             // [27][N], or NULL
-  double* partials;        // [carrier_xy_records][kCStat] records of the slab, or NULL
+  float* f_sgs;            // carrier: [27][N], or NULL
+  float* f_h2;             // carrier: [27][N], or NULL
+  float* m3;               // third-order moment: [10][N], or NULL
+  float* theta_t;          // Favre temperature: [N], or NULL
+  double* partials;        // [mono_xy_records][statistics] records of the slab, or NULL
 };
-int carrier_tile_x();               // the x-y tile
-int carrier_tile_y();
-int64_t carrier_xy_records(const CarrierArgs& a);  // statistics records of one slab
-int carrier_z_planes(int fp64);     // planes per thread of the z pass
-hipError_t launch_carrier_z(const CarrierArgs& a, int R, int fp64, hipStream_t s);
-hipError_t launch_carrier_xy(const CarrierArgs& a, int R, int fp64, hipStream_t s);
+int mono_tile_x();                  // the x-y tile
+int mono_tile_y();
+int mono_z_planes(int fp64);        // planes per thread of the z pass
+int64_t mono_xy_records(const MonoArgs& a);  // statistics records of one slab
+hipError_t launch_mono_z(const MonoArgs& a, int set, int R, int fp64, hipStream_t s);
+hipError_t launch_mono_xy(const MonoArgs& a, int set, int R, int fp64, hipStream_t s);
 
 // box kernels (kcf_box.hip)
 struct BoxGeom {

@@ -1,10 +1,18 @@
-// A priori SGS carrier of the D3Q27 lattice: f_sgs,i = bar(f0_i(rho, u)) - f0_i(rho_bar, ut)
-// (eqs. f0bar and fsgs_def) with the product equilibrium of eq. discrete_equilibrium, and the
-// second-order Hermite reconstruction of the KC-MP closure from tau (eq. f_sgs_KCMP).
+// Filtered monomials rho u_x^a u_y^b u_z^c (and rho theta) and the SGS quantities built from
+// them, as two streaming kernels per z slab shared by two quantity sets:
 //
-// With velocities in units of sqrt(theta_R) and xh = xi / sqrt(theta_R) in {0, +-sqrt3}, the
-// equilibrium is w_i rho prod_a (P_0 + P_1(xh_ia) u_a + P_2(xh_ia) u_a^2) with the D1Q3
-// Hermite polynomials P_0 = 1, P_1 = xh, P_2 = (xh^2 - 1)/2. The filter is linear, hence
+//   carrier  the a priori SGS carrier of the D3Q27 lattice, f_sgs,i = bar(f0_i(rho, u)) -
+//            f0_i(rho_bar, ut) (eqs. f0bar and fsgs_def) with the product equilibrium of
+//            eq. discrete_equilibrium, and the second-order Hermite reconstruction of the KC-MP
+//            closure from tau (eq. f_sgs_KCMP);
+//   moment3  the third-order SGS moment m3_ijk = bar(rho u_i u_j u_k) - rho_bar ut_i ut_j ut_k
+//            (the order-3 term of eq. f_sgs_hermite) and the Favre temperature
+//            bar(rho theta) / rho_bar (definition after eq. f0resolved).
+//
+// Carrier. With velocities in units of sqrt(theta_R) and xh = xi / sqrt(theta_R) in
+// {0, +-sqrt3}, the equilibrium is w_i rho prod_a (P_0 + P_1(xh_ia) u_a + P_2(xh_ia) u_a^2)
+// with the D1Q3 Hermite polynomials P_0 = 1, P_1 = xh, P_2 = (xh^2 - 1)/2. The filter is
+// linear, hence
 //   f_sgs,i = w_i sum_abc P_a(xh_ix) P_b(xh_iy) P_c(xh_iz) D_abc,
 //   D_abc   = bar(rho u_x^a u_y^b u_z^c) - rho_bar ut_x^a ut_y^b ut_z^c,     a, b, c in 0..2:
 // 27 filtered monomials replace 27 filtered populations, and the subtraction happens where
@@ -12,18 +20,17 @@
 // degree-2 D are tau, whose terms alone form the reconstruction f_h2. The total degree is the
 // Hermite order of a term (eq. f_sgs_hermite on the tensor-product lattice).
 //
-// Two kernels per z slab:
-//   k_carrier_z   one thread per (x, y) column and ZT planes: the monomials of the input,
-//                 nine at a time (one power of u_z), filtered along z over a register window
-//                 of the input planes and written to the slab buffer [27][planes][ny][nx];
-//   k_carrier_xy  one workgroup per (kTX x kTY tile, run of eight planes), XCD-banded: per plane,
-//                 the monomials of the tile and its halo staged in LDS G at a time, filtered
-//                 along x and y in place, each thread keeping its point's 27 filtered
-//                 monomials; then D, the Hermite synthesis of f_sgs and f_h2, the stores and
-//                 the statistics (a point's sums over its populations in FP32, their sums over
-//                 points in FP64, one record per workgroup).
-// T is the type of the monomials, of both filter passes, of the slab buffer and of D (double
-// for narrow widths, as in the Favre path); the synthesis from D runs in FP32.
+//   k_*_z   one thread per (x, y) column and ZT planes: the set's products of the input,
+//           one group of up to nine at a time, filtered along z over a register window of
+//           the input planes and written to the slab buffer [quantities][planes][ny][nx];
+//   k_*_xy  one workgroup per (kTX x kTY tile, run of eight planes), XCD-banded: per plane,
+//           the quantities of the tile and its halo staged in LDS G at a time, filtered along
+//           x and y in place, each thread keeping its point's filtered values; then the set's
+//           epilogue (stores and statistics: a point's values in FP32, their sums over points
+//           in FP64, one record per workgroup).
+// T is the type of the products, of both filter passes and of the slab buffer (double for
+// narrow widths, as in the Favre path); the differences against the Favre fields are formed
+// in T, what follows them in FP32.
 #include "kcf_device.h"
 
 namespace kcf {
@@ -32,23 +39,24 @@ namespace {
 
 using namespace dev;
 
-constexpr int kZB = 256;  // threads of k_carrier_z
-constexpr int kTX = 16;   // tile of k_carrier_xy: kTX x kTY points, one per thread
+constexpr int kZB = 256;  // threads of the z kernels
+constexpr int kTX = 16;   // tile of the x-y kernels: kTX x kTY points, one per thread
 constexpr int kTY = 16;
-constexpr int kXT = 256;  // threads of k_carrier_xy (one per tile point)
-constexpr int kLook = 3;  // input planes in flight ahead of the FMAs in k_carrier_z
-constexpr int kXZ = 8;    // planes per workgroup of k_carrier_xy
+constexpr int kXT = 256;  // threads of the x-y kernels (one per tile point)
+constexpr int kLook = 3;  // input planes in flight ahead of the FMAs in the z kernels
+constexpr int kXZ = 8;    // planes per workgroup of the x-y kernels
 
 template <typename T>
 constexpr int cz_planes() { return sizeof(T) == 8 ? 8 : 16; }
 
 template <typename T>
-__device__ __forceinline__ const T* cweights(const CarrierArgs& A);
+__device__ __forceinline__ const T* cweights(const MonoArgs& A);
 template <>
-__device__ __forceinline__ const float* cweights<float>(const CarrierArgs& A) { return A.w; }
+__device__ __forceinline__ const float* cweights<float>(const MonoArgs& A) { return A.w; }
 template <>
-__device__ __forceinline__ const double* cweights<double>(const CarrierArgs& A) { return A.wd; }
+__device__ __forceinline__ const double* cweights<double>(const MonoArgs& A) { return A.wd; }
 
+// ---------------------------------------------------------------- the SGS carrier
 // Monomial m = a + 3 b + 9 c stands for rho u_x^a u_y^b u_z^c.
 __host__ __device__ constexpr int mono_deg(int m) { return m % 3 + (m / 3) % 3 + m / 9; }
 // weighted norm n_a n_b n_c of the basis term, n = (1, 1, 1/2)
@@ -56,123 +64,20 @@ __host__ __device__ constexpr double mono_norm(int m) {
   return (m % 3 == 2 ? 0.5 : 1.0) * ((m / 3) % 3 == 2 ? 0.5 : 1.0) * (m / 9 == 2 ? 0.5 : 1.0);
 }
 
-// Loads of the input plane zz at the column of byte offset cb (< 2^32 since a plane holds at
-// most 2^30 points): uniform plane pointers plus a 32-bit per-lane offset.
-__device__ __forceinline__ void load_inputs(const CarrierArgs& A, int zz, uint32_t cb,
-                                            float (&v)[4]) {
-  const int64_t zo = (int64_t)zz * A.nx * A.ny;
-  const char* pr = reinterpret_cast<const char*>(A.rho + zo);
-  const char* pu = reinterpret_cast<const char*>(A.u + zo);
-  const int64_t nb = A.ntot * (int64_t)sizeof(float);
-  v[0] = *reinterpret_cast<const float*>(pr + cb);
-  v[1] = *reinterpret_cast<const float*>(pu + cb);
-  v[2] = *reinterpret_cast<const float*>(pu + nb + cb);
-  v[3] = *reinterpret_cast<const float*>(pu + 2 * nb + cb);
-}
-
-// Two waves per SIMD: the register budget then bounds how far the scheduler hoists the
-// window loads ahead of their FMAs.
-template <int R, typename T>
-__global__ void __launch_bounds__(kZB) __attribute__((amdgpu_waves_per_eu(2, 2)))
-k_carrier_z(CarrierArgs A) {
-  constexpr int ZT = cz_planes<T>();
-  constexpr int NJ = ZT + 2 * R;  // input planes z0 - R .. z0 + ZT + R - 1 of the window
-  const int x = blockIdx.x * kZB + threadIdx.x;
-  if (x >= A.nx) return;
-  const int y = blockIdx.y;
-  const int zl0 = blockIdx.z * ZT;  // first plane of the thread, relative to the slab
-  const int nk = min(ZT, A.nzs - zl0);
-  const int64_t plane = (int64_t)A.nx * A.ny;
-  const uint32_t cb = (uint32_t)(y * A.nx + x) * (uint32_t)sizeof(float);
-  const int64_t qstride = (int64_t)A.nzs * plane;
-  const T* w = cweights<T>(A);
-  T* out = reinterpret_cast<T*>(A.zbuf) + (int64_t)zl0 * plane + (int64_t)y * A.nx + x;
-#pragma unroll 1
-  for (int c = 0; c < 3; ++c) {
-    T acc[9][ZT];
-#pragma unroll
-    for (int q = 0; q < 9; ++q)
-#pragma unroll
-      for (int k = 0; k < ZT; ++k) acc[q][k] = (T)0;
-    // first window plane, made opaque per monomial group so that the plane offsets are
-    // recomputed (two scalar ops a plane) rather than held for all groups
-    int zz = wrapi(A.zs + zl0 - R, A.nz);
-    __asm__ volatile("" : "+s"(zz));
-    float in[kLook][4];  // planes in flight
-#pragma unroll
-    for (int j = 0; j < kLook; ++j) {
-      load_inputs(A, zz, cb, in[j]);
-      zz = zz + 1 == A.nz ? 0 : zz + 1;
-    }
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const T r = (T)in[j % kLook][0];
-      const T vx = (T)in[j % kLook][1], vy = (T)in[j % kLook][2], vz = (T)in[j % kLook][3];
-      if (j + kLook < NJ) {
-        load_inputs(A, zz, cb, in[j % kLook]);
-        zz = zz + 1 == A.nz ? 0 : zz + 1;
-      }
-      // keep the later loads below this point: the window is not held in registers
-      __builtin_amdgcn_sched_barrier(0);
-      T b0 = r;
-      if (c >= 1) b0 = b0 * vz;
-      if (c == 2) b0 = b0 * vz;
-      T p[9];  // p[a + 3 b] = rho u_z^c u_y^b u_x^a
-      T yb = b0;
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        if (b > 0) yb = yb * vy;
-        p[3 * b] = yb;
-        p[3 * b + 1] = yb * vx;
-        p[3 * b + 2] = p[3 * b + 1] * vx;
-      }
-#pragma unroll
-      for (int k = 0; k < ZT; ++k) {
-        const int t = j - k;  // tap of plane j for output k
-        if (t >= 0 && t <= 2 * R) {
-#pragma unroll
-          for (int q = 0; q < 9; ++q) acc[q][k] = fma(w[t], p[q], acc[q][k]);
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      T* o = out + (int64_t)(9 * c + q) * qstride;
-#pragma unroll
-      for (int k = 0; k < ZT; ++k)
-        if (k < nk) o[(int64_t)k * plane] = acc[q][k];
-    }
-  }
-}
-
-template <int R, typename T>
-struct CarrierLds {
-  static constexpr int HX = kTX + 2 * R;
-  static constexpr int HY = kTY + 2 * R;
-  static constexpr int HXP = HX | 1;  // odd row stride
-  static constexpr int NRAW = HX * HY;
-  static constexpr int QS = HY * HXP;
-  // monomials per LDS round: nine while they fit in 64 KiB, else three
-  static constexpr int G = 9 * QS * (int)sizeof(T) <= 65536 ? 9 : 3;
-  static constexpr int doubles = (G * QS * (int)sizeof(T) + 7) / 8;
-};
-
 // One direction of the Hermite synthesis, in place: coefficients (d_0, d_1, d_2) of P_0, P_1,
 // P_2 to the values at xh = -sqrt3, 0, +sqrt3, times the D1Q3 weights 1/6, 2/3, 1/6.
-template <typename T>
-__device__ __forceinline__ void synth1(T& v0, T& v1, T& v2) {
-  const T s = v0 + v2;
-  const T t = (T)1.7320508075688772 * v1;
-  const T mid = v0 - (T)0.5 * v2;
-  v0 = (s - t) * (T)(1.0 / 6.0);
-  v1 = mid * (T)(2.0 / 3.0);
-  v2 = (s + t) * (T)(1.0 / 6.0);
+__device__ __forceinline__ void synth1(float& v0, float& v1, float& v2) {
+  const float s = v0 + v2;
+  const float t = 1.7320508075688772f * v1;
+  const float mid = v0 - 0.5f * v2;
+  v0 = (s - t) * (float)(1.0 / 6.0);
+  v1 = mid * (float)(2.0 / 3.0);
+  v2 = (s + t) * (float)(1.0 / 6.0);
 }
 
 // d[a + 3 b + 9 c] = D_abc in, d[ix + 3 iy + 9 iz] = f of the population (ix - 1, iy - 1,
 // iz - 1) out: z, then y, then x.
-template <typename T>
-__device__ __forceinline__ void synth(T (&d)[27]) {
+__device__ __forceinline__ void synth(float (&d)[27]) {
 #pragma unroll
   for (int ab = 0; ab < 9; ++ab) synth1(d[ab], d[ab + 9], d[ab + 18]);
 #pragma unroll
@@ -183,73 +88,36 @@ __device__ __forceinline__ void synth(T (&d)[27]) {
   for (int yz = 0; yz < 9; ++yz) synth1(d[3 * yz], d[3 * yz + 1], d[3 * yz + 2]);
 }
 
-template <int R, typename T>
-__global__ void __launch_bounds__(kXT) k_carrier_xy(CarrierArgs A) {
-  using L = CarrierLds<R, T>;
-  constexpr int HX = L::HX, HY = L::HY, HXP = L::HXP, QS = L::QS, G = L::G;
-  __shared__ double smem[L::doubles];
-  T* buf = reinterpret_cast<T*>(smem);
-  // item = (tile, run of kXZ planes); XCD bands: consecutive items (neighbouring tiles, which
-  // share halos) on one XCD
-  const int nzc = (A.nzs + kXZ - 1) / kXZ;
-  const int nb = A.ntiles * nzc;
-  const int per = (nb + 7) / 8;
-  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
-  if (item >= nb) return;
-  const int tile = item % A.ntiles, zc = item / A.ntiles;
-  const int x0 = (tile % A.ntx) * kTX, y0 = (tile / A.ntx) * kTY;
-  const int tid = threadIdx.x, px = tid % kTX, py = tid / kTX;
-  const int64_t plane = (int64_t)A.nx * A.ny;
-  const int64_t qstride = (int64_t)A.nzs * plane;
-  const T* w = cweights<T>(A);
-  const bool valid = x0 + px < A.nx && y0 + py < A.ny;
-  double acc[kCStat];  // this thread's FP64 sums over its points
+struct CarrierSet {
+  static constexpr int kQ = 27;      // quantities: monomial m = a + 3 b + 9 c
+  static constexpr int kGroups = 3;  // z-pass groups: one power c of u_z each
+  static constexpr int kGS = 9;      // products per group
+  static constexpr int kStat = kCStat;
+  static constexpr bool kStaticGroups = false;  // one code copy, group index at run time
+  static constexpr bool kOptionalLast = false;  // every quantity always filtered
+
+  // products of group g: p[a + 3 b] = rho u_z^g u_y^b u_x^a
+  template <int GRP, typename T>
+  __device__ static void products(int g, T r, T vx, T vy, T vz, T, T (&p)[kGS]) {
+    T b0 = r;
+    if (g >= 1) b0 = b0 * vz;
+    if (g == 2) b0 = b0 * vz;
+    T yb = b0;
 #pragma unroll
-  for (int k = 0; k < kCStat; ++k) acc[k] = 0.0;
-  const int z_hi = min((zc + 1) * kXZ, A.nzs);
-  for (int zl = zc * kXZ; zl < z_hi; ++zl) {
-    const T* zb = reinterpret_cast<const T*>(A.zbuf) + (int64_t)zl * plane;
-    T M[27];
-#pragma unroll
-    for (int g0 = 0; g0 < 27; g0 += G) {
-      for (int r = tid; r < L::NRAW; r += kXT) {
-        const int hx = r % HX, hy = r / HX;
-        const int64_t o = (int64_t)wrapi(y0 - R + hy, A.ny) * A.nx + wrapi(x0 - R + hx, A.nx);
-        T* d = buf + hy * HXP + hx;
-#pragma unroll
-        for (int q = 0; q < G; ++q) d[q * QS] = zb[(int64_t)(g0 + q) * qstride + o];
-      }
-      __syncthreads();
-      // x, in place: one (monomial, row) per task
-      for (int t = tid; t < G * HY; t += kXT) {
-        T* v = buf + t * HXP;
-        T vr[HX];
-#pragma unroll
-        for (int i = 0; i < HX; ++i) vr[i] = v[i];
-#pragma unroll
-        for (int o = 0; o < kTX; ++o) v[o] = tap_sum<R, T>(w, vr, o + R);
-      }
-      __syncthreads();
-      // y, in place: one (monomial, column) per task, outputs to rows 0 .. kTY - 1
-      for (int t = tid; t < G * kTX; t += kXT) {
-        T* v = buf + (t / kTX) * QS + t % kTX;
-        T vr[HY];
-#pragma unroll
-        for (int i = 0; i < HY; ++i) vr[i] = v[i * HXP];
-#pragma unroll
-        for (int o = 0; o < kTY; ++o) v[o * HXP] = tap_sum<R, T>(w, vr, o + R);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < G; ++q) M[g0 + q] = buf[q * QS + py * HXP + px];
-      __syncthreads();
+    for (int b = 0; b < 3; ++b) {
+      if (b > 0) yb = yb * vy;
+      p[3 * b] = yb;
+      p[3 * b + 1] = yb * vx;
+      p[3 * b + 2] = p[3 * b + 1] * vx;
     }
-    // ---- Favre velocity and D_abc
+  }
+
+  template <typename T>
+  __device__ static void epilogue(const MonoArgs& A, const T (&M)[kQ], bool valid, int64_t g,
+                                  double (&acc)[kStat]) {
     const T rb = M[0];
     const T ri = (T)1 / rb;
     const T uv[3] = {M[1] * ri, M[3] * ri, M[9] * ri};
-    // D is a small difference of large filtered monomials and is formed in T; the Hermite
-    // synthesis that follows is a well-conditioned linear map and runs in FP32.
     float D[27];
     float herm[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // weighted energies of Hermite orders 2..6
 #pragma unroll
@@ -271,7 +139,6 @@ __global__ void __launch_bounds__(kXT) k_carrier_xy(CarrierArgs A) {
     // tau = degree-2 D: xx xy xz yy yz zz
     const float txx = D[2], txy = D[4], txz = D[10], tyy = D[6], tyz = D[12], tzz = D[18];
     synth(D);
-    const int64_t g = (int64_t)(A.zs + zl) * plane + (int64_t)(y0 + py) * A.nx + x0 + px;
     float sf2 = 0.f, serr = 0.f;
     // population i = 9 (c_x + 1) + 3 (c_y + 1) + (c_z + 1)
 #pragma unroll
@@ -303,7 +170,6 @@ __global__ void __launch_bounds__(kXT) k_carrier_xy(CarrierArgs A) {
         }
       }
     }
-    // the point's sums (FP32 over its 27 populations) join the FP64 accumulators
     const bool finite = isfinite(sf2 + serr + herm[0] + herm[1] + herm[2] + herm[3] + herm[4]);
     const bool use = valid && finite;
     acc[C_N] += use ? 1.0 : 0.0;
@@ -313,45 +179,341 @@ __global__ void __launch_bounds__(kXT) k_carrier_xy(CarrierArgs A) {
     for (int k = 0; k < 5; ++k) acc[C_HERM + k] += use ? (double)herm[k] : 0.0;
     acc[C_NONFINITE] += valid && !finite ? 1.0 : 0.0;
   }
+};
+
+// ---------------------------------------------------------------- third-order moment
+// Quantities: 0 rho, 1..3 rho u_x, rho u_y, rho u_z, 4..13 rho u_i u_j u_k in the order
+// xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz, 14 rho theta (filtered only with a temperature).
+struct Moment3Set {
+  static constexpr int kQ = 15;
+  static constexpr int kGroups = 2;
+  static constexpr int kGS = 8;  // groups of eight (the last slot of the second is unused)
+  static constexpr int kStat = kM3Stat;
+  static constexpr bool kStaticGroups = true;  // a code copy per group
+  static constexpr bool kOptionalLast = true;  // rho theta only with a temperature
+
+  template <int GRP, typename T>
+  __device__ static void products(int, T r, T vx, T vy, T vz, T th, T (&p)[kGS]) {
+    const T rx = r * vx, ry = r * vy, rz = r * vz;
+    if constexpr (GRP == 0) {
+      const T rxx = rx * vx;
+      p[0] = r;
+      p[1] = rx;
+      p[2] = ry;
+      p[3] = rz;
+      p[4] = rxx * vx;        // xxx
+      p[5] = rxx * vy;        // xxy
+      p[6] = rxx * vz;        // xxz
+      p[7] = (rx * vy) * vy;  // xyy
+    } else {
+      const T ryy = ry * vy, rzz = rz * vz;
+      p[0] = (rx * vy) * vz;  // xyz
+      p[1] = rx * vz * vz;    // xzz
+      p[2] = ryy * vy;        // yyy
+      p[3] = ryy * vz;        // yyz
+      p[4] = ry * vz * vz;    // yzz
+      p[5] = rzz * vz;        // zzz
+      p[6] = r * th;          // rho theta
+      p[7] = (T)0;
+    }
+  }
+
+  template <typename T>
+  __device__ static void epilogue(const MonoArgs& A, const T (&M)[kQ], bool valid, int64_t g,
+                                  double (&acc)[kStat]) {
+    const T rb = M[0];
+    const T ri = (T)1 / rb;
+    const T uv[3] = {M[1] * ri, M[2] * ri, M[3] * ri};
+    constexpr int ia[10] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 2};
+    constexpr int ja[10] = {0, 0, 0, 1, 1, 2, 1, 1, 2, 2};
+    constexpr int ka[10] = {0, 1, 2, 1, 2, 2, 1, 2, 2, 2};
+    float m3[10];
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < 10; ++c) {
+      m3[c] = (float)(M[4 + c] - ((rb * uv[ia[c]]) * uv[ja[c]]) * uv[ka[c]]);
+      s += m3[c];
+    }
+    const float tt = A.theta ? (float)(M[14] * ri) : 1.f;
+    if (valid) {
+      if (A.m3) {
+#pragma unroll
+        for (int c = 0; c < 10; ++c) A.m3[(int64_t)c * A.ntot + g] = m3[c];
+      }
+      if (A.theta_t) A.theta_t[g] = tt;
+    }
+    const bool finite = isfinite(s + tt);
+    const bool use = valid && finite;
+    acc[M3_N] += use ? 1.0 : 0.0;
+#pragma unroll
+    for (int c = 0; c < 10; ++c) {
+      acc[M3_SUM + c] += use ? (double)m3[c] : 0.0;
+      acc[M3_SQ + c] += use ? (double)(m3[c] * m3[c]) : 0.0;
+    }
+    acc[M3_THETA] += use ? (double)tt : 0.0;
+    acc[M3_NONFINITE] += valid && !finite ? 1.0 : 0.0;
+  }
+};
+
+// ---------------------------------------------------------------- the two passes
+// Loads of the input plane zz at the column of byte offset cb (< 2^32 since a plane holds at
+// most 2^30 points): uniform plane pointers plus a 32-bit per-lane offset. v[4] is the
+// temperature (1 without one).
+__device__ __forceinline__ void load_inputs(const MonoArgs& A, int zz, uint32_t cb,
+                                            float (&v)[5]) {
+  const int64_t zo = (int64_t)zz * A.nx * A.ny;
+  const char* pr = reinterpret_cast<const char*>(A.rho + zo);
+  const char* pu = reinterpret_cast<const char*>(A.u + zo);
+  const int64_t nb = A.ntot * (int64_t)sizeof(float);
+  v[0] = *reinterpret_cast<const float*>(pr + cb);
+  v[1] = *reinterpret_cast<const float*>(pu + cb);
+  v[2] = *reinterpret_cast<const float*>(pu + nb + cb);
+  v[3] = *reinterpret_cast<const float*>(pu + 2 * nb + cb);
+  v[4] = A.theta ? *reinterpret_cast<const float*>(reinterpret_cast<const char*>(A.theta + zo) + cb)
+                 : 1.f;
+}
+
+// One group of products (GRP >= 0: fixed at compile time; -1: grp at run time) for the ZT
+// planes of one column.
+template <class S, int R, typename T, int GRP>
+__device__ __forceinline__ void z_group(const MonoArgs& A, int grp, int zl0, int nk,
+                                        uint32_t cb, T* out) {
+  constexpr int ZT = cz_planes<T>();
+  constexpr int NJ = ZT + 2 * R;  // input planes z0 - R .. z0 + ZT + R - 1 of the window
+  constexpr int GS = S::kGS;
+  const int64_t plane = (int64_t)A.nx * A.ny;
+  const int64_t qstride = (int64_t)A.nzs * plane;
+  const T* w = cweights<T>(A);
+  T acc[GS][ZT];
+#pragma unroll
+  for (int q = 0; q < GS; ++q)
+#pragma unroll
+    for (int k = 0; k < ZT; ++k) acc[q][k] = (T)0;
+  // first window plane, made opaque per group so that the plane offsets are recomputed (two
+  // scalar ops a plane) rather than held for all groups
+  int zz = wrapi(A.zs + zl0 - R, A.nz);
+  __asm__ volatile("" : "+s"(zz));
+  float in[kLook][5];  // planes in flight
+#pragma unroll
+  for (int j = 0; j < kLook; ++j) {
+    load_inputs(A, zz, cb, in[j]);
+    zz = zz + 1 == A.nz ? 0 : zz + 1;
+  }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const float(&v)[5] = in[j % kLook];
+    const T r = (T)v[0], vx = (T)v[1], vy = (T)v[2], vz = (T)v[3], th = (T)v[4];
+    if (j + kLook < NJ) {
+      load_inputs(A, zz, cb, in[j % kLook]);
+      zz = zz + 1 == A.nz ? 0 : zz + 1;
+    }
+    // keep the later loads below this point: the window is not held in registers
+    __builtin_amdgcn_sched_barrier(0);
+    T p[GS];
+    S::template products<GRP>(grp, r, vx, vy, vz, th, p);
+#pragma unroll
+    for (int k = 0; k < ZT; ++k) {
+      const int t = j - k;  // tap of plane j for output k
+      if (t >= 0 && t <= 2 * R) {
+#pragma unroll
+        for (int q = 0; q < GS; ++q) acc[q][k] = fma(w[t], p[q], acc[q][k]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < GS; ++q) {
+    const int qq = grp * GS + q;
+    if (qq < A.nq) {
+      T* o = out + (int64_t)qq * qstride;
+#pragma unroll
+      for (int k = 0; k < ZT; ++k)
+        if (k < nk) o[(int64_t)k * plane] = acc[q][k];
+    }
+  }
+}
+
+template <class S, int R, typename T>
+__device__ __forceinline__ void z_pass(const MonoArgs& A) {
+  constexpr int ZT = cz_planes<T>();
+  const int x = blockIdx.x * kZB + threadIdx.x;
+  if (x >= A.nx) return;
+  const int y = blockIdx.y;
+  const int zl0 = blockIdx.z * ZT;  // first plane of the thread, relative to the slab
+  const int nk = min(ZT, A.nzs - zl0);
+  const int64_t plane = (int64_t)A.nx * A.ny;
+  const uint32_t cb = (uint32_t)(y * A.nx + x) * (uint32_t)sizeof(float);
+  T* out = reinterpret_cast<T*>(A.zbuf) + (int64_t)zl0 * plane + (int64_t)y * A.nx + x;
+  if constexpr (S::kStaticGroups) {
+    static_assert(S::kGroups == 2, "static groups are unrolled for two groups");
+    z_group<S, R, T, 0>(A, 0, zl0, nk, cb, out);
+    z_group<S, R, T, 1>(A, 1, zl0, nk, cb, out);
+  } else {
+#pragma unroll 1
+    for (int grp = 0; grp < S::kGroups; ++grp) z_group<S, R, T, -1>(A, grp, zl0, nk, cb, out);
+  }
+}
+
+template <int R, typename T, int NQ>
+struct XyLds {
+  static constexpr int HX = kTX + 2 * R;
+  static constexpr int HY = kTY + 2 * R;
+  static constexpr int HXP = HX | 1;  // odd row stride
+  static constexpr int NRAW = HX * HY;
+  static constexpr int QS = HY * HXP;
+  // quantities per LDS round: nine while they fit in 64 KiB, else three
+  static constexpr int G = 9 * QS * (int)sizeof(T) <= 65536 ? 9 : 3;
+  static constexpr int doubles = (G * QS * (int)sizeof(T) + 7) / 8;
+};
+
+template <class S, int R, typename T>
+__device__ __forceinline__ void xy_pass(const MonoArgs& A) {
+  using L = XyLds<R, T, S::kQ>;
+  constexpr int HX = L::HX, HY = L::HY, HXP = L::HXP, QS = L::QS, G = L::G;
+  constexpr int NQ = S::kQ;
+  constexpr int NS = S::kStat;
+  static_assert(4 * NS <= L::doubles, "statistics records do not fit the LDS buffer");
+  __shared__ double smem[L::doubles];
+  T* buf = reinterpret_cast<T*>(smem);
+  // item = (tile, run of kXZ planes); XCD bands: consecutive items (neighbouring tiles, which
+  // share halos) on one XCD
+  const int nzc = (A.nzs + kXZ - 1) / kXZ;
+  const int nb = A.ntiles * nzc;
+  const int per = (nb + 7) / 8;
+  const int item = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (item >= nb) return;
+  const int tile = item % A.ntiles, zc = item / A.ntiles;
+  const int x0 = (tile % A.ntx) * kTX, y0 = (tile / A.ntx) * kTY;
+  const int tid = threadIdx.x, px = tid % kTX, py = tid / kTX;
+  const int64_t plane = (int64_t)A.nx * A.ny;
+  const int64_t qstride = (int64_t)A.nzs * plane;
+  const T* w = cweights<T>(A);
+  const bool valid = x0 + px < A.nx && y0 + py < A.ny;
+  double acc[NS];  // this thread's FP64 sums over its points
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+  const int z_hi = min((zc + 1) * kXZ, A.nzs);
+  for (int zl = zc * kXZ; zl < z_hi; ++zl) {
+    const T* zb = reinterpret_cast<const T*>(A.zbuf) + (int64_t)zl * plane;
+    T M[NQ];
+#pragma unroll
+    for (int g0 = 0; g0 < NQ; g0 += G) {
+      // quantities of this round (uniform; fixed unless the last quantity is optional)
+      const int ng = S::kOptionalLast ? min(G, A.nq - g0) : min(G, NQ - g0);
+      for (int r = tid; r < L::NRAW; r += kXT) {
+        const int hx = r % HX, hy = r / HX;
+        const int64_t o = (int64_t)wrapi(y0 - R + hy, A.ny) * A.nx + wrapi(x0 - R + hx, A.nx);
+        T* d = buf + hy * HXP + hx;
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+          if (g0 + q < NQ && q < ng) d[q * QS] = zb[(int64_t)(g0 + q) * qstride + o];
+      }
+      __syncthreads();
+      // x, in place: one (quantity, row) per task
+      for (int t = tid; t < ng * HY; t += kXT) {
+        T* v = buf + t * HXP;
+        T vr[HX];
+#pragma unroll
+        for (int i = 0; i < HX; ++i) vr[i] = v[i];
+#pragma unroll
+        for (int o = 0; o < kTX; ++o) v[o] = tap_sum<R, T>(w, vr, o + R);
+      }
+      __syncthreads();
+      // y, in place: one (quantity, column) per task, outputs to rows 0 .. kTY - 1
+      for (int t = tid; t < ng * kTX; t += kXT) {
+        T* v = buf + (t / kTX) * QS + t % kTX;
+        T vr[HY];
+#pragma unroll
+        for (int i = 0; i < HY; ++i) vr[i] = v[i * HXP];
+#pragma unroll
+        for (int o = 0; o < kTY; ++o) v[o * HXP] = tap_sum<R, T>(w, vr, o + R);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < G; ++q)
+        if (g0 + q < NQ) M[g0 + q] = q < ng ? buf[q * QS + py * HXP + px] : (T)0;
+      __syncthreads();
+    }
+    const int64_t g = (int64_t)(A.zs + zl) * plane + (int64_t)(y0 + py) * A.nx + x0 + px;
+    S::epilogue(A, M, valid, g, acc);
+  }
   if (!A.partials) return;
   // ---- fixed-order wave and block reduction, one record per workgroup
 #pragma unroll
-  for (int k = 0; k < kCStat; ++k) {
+  for (int k = 0; k < NS; ++k) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) acc[k] += __shfl_xor(acc[k], d);
   }
   if (__lane_id() == 0) {
 #pragma unroll
-    for (int k = 0; k < kCStat; ++k) smem[(tid >> 6) * kCStat + k] = acc[k];
+    for (int k = 0; k < NS; ++k) smem[(tid >> 6) * NS + k] = acc[k];
   }
   __syncthreads();
-  if (tid < kCStat) {
+  if (tid < NS) {
     double a = 0;
 #pragma unroll
-    for (int wv = 0; wv < kXT / 64; ++wv) a += smem[wv * kCStat + tid];
-    A.partials[(int64_t)item * kCStat + tid] = a;
+    for (int wv = 0; wv < kXT / 64; ++wv) a += smem[wv * NS + tid];
+    A.partials[(int64_t)item * NS + tid] = a;
   }
 }
 
+// Two waves per SIMD for the z kernels: the register budget then bounds how far the
+// scheduler hoists the window loads ahead of their FMAs.
+template <int R, typename T>
+__global__ void __launch_bounds__(kZB) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_carrier_z(MonoArgs A) {
+  z_pass<CarrierSet, R, T>(A);
+}
+
+template <int R, typename T>
+__global__ void __launch_bounds__(kXT) k_carrier_xy(MonoArgs A) {
+  xy_pass<CarrierSet, R, T>(A);
+}
+
+template <int R, typename T>
+__global__ void __launch_bounds__(kZB) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_moment3_z(MonoArgs A) {
+  z_pass<Moment3Set, R, T>(A);
+}
+
+template <int R, typename T>
+__global__ void __launch_bounds__(kXT) k_moment3_xy(MonoArgs A) {
+  xy_pass<Moment3Set, R, T>(A);
+}
+
+// ---------------------------------------------------------------- launches
 template <int R>
-hipError_t launch_z_of(const CarrierArgs& a, int fp64, hipStream_t s) {
+hipError_t launch_z_of(const MonoArgs& a, int set, int fp64, hipStream_t s) {
   const int zt = fp64 ? cz_planes<double>() : cz_planes<float>();
   const dim3 grid((a.nx + kZB - 1) / kZB, a.ny, (a.nzs + zt - 1) / zt);
-  if (fp64)
-    hipLaunchKernelGGL((k_carrier_z<R, double>), grid, dim3(kZB), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_carrier_z<R, float>), grid, dim3(kZB), 0, s, a);
+  if (set == kSetCarrier) {
+    if (fp64)
+      hipLaunchKernelGGL((k_carrier_z<R, double>), grid, dim3(kZB), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_carrier_z<R, float>), grid, dim3(kZB), 0, s, a);
+  } else {
+    if (fp64)
+      hipLaunchKernelGGL((k_moment3_z<R, double>), grid, dim3(kZB), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_moment3_z<R, float>), grid, dim3(kZB), 0, s, a);
+  }
   return hipGetLastError();
 }
 
 template <int R>
-hipError_t launch_xy_of(const CarrierArgs& a, int fp64, hipStream_t s) {
-  const int64_t nb = carrier_xy_records(a);
+hipError_t launch_xy_of(const MonoArgs& a, int set, int fp64, hipStream_t s) {
+  const int64_t nb = mono_xy_records(a);
   const dim3 grid((unsigned)(8 * ((nb + 7) / 8)));
-  if (fp64)
-    hipLaunchKernelGGL((k_carrier_xy<R, double>), grid, dim3(kXT), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_carrier_xy<R, float>), grid, dim3(kXT), 0, s, a);
+  if (set == kSetCarrier) {
+    if (fp64)
+      hipLaunchKernelGGL((k_carrier_xy<R, double>), grid, dim3(kXT), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_carrier_xy<R, float>), grid, dim3(kXT), 0, s, a);
+  } else {
+    if (fp64)
+      hipLaunchKernelGGL((k_moment3_xy<R, double>), grid, dim3(kXT), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_moment3_xy<R, float>), grid, dim3(kXT), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -376,29 +538,33 @@ hipError_t dispatch_r(int R, Args... args) {
 
 template <int R>
 struct RunZ {
-  static hipError_t run(const CarrierArgs& a, int fp64, hipStream_t s) { return launch_z_of<R>(a, fp64, s); }
+  static hipError_t run(const MonoArgs& a, int set, int fp64, hipStream_t s) {
+    return launch_z_of<R>(a, set, fp64, s);
+  }
 };
 template <int R>
 struct RunXY {
-  static hipError_t run(const CarrierArgs& a, int fp64, hipStream_t s) { return launch_xy_of<R>(a, fp64, s); }
+  static hipError_t run(const MonoArgs& a, int set, int fp64, hipStream_t s) {
+    return launch_xy_of<R>(a, set, fp64, s);
+  }
 };
 
 }  // namespace
 
-int carrier_tile_x() { return kTX; }
-int carrier_tile_y() { return kTY; }
-int64_t carrier_xy_records(const CarrierArgs& a) {
+int mono_tile_x() { return kTX; }
+int mono_tile_y() { return kTY; }
+int mono_z_planes(int fp64) { return fp64 ? cz_planes<double>() : cz_planes<float>(); }
+int64_t mono_xy_records(const MonoArgs& a) {
   return (int64_t)a.ntiles * ((a.nzs + kXZ - 1) / kXZ);
 }
-int carrier_z_planes(int fp64) { return fp64 ? cz_planes<double>() : cz_planes<float>(); }
 
-hipError_t launch_carrier_z(const CarrierArgs& a, int R, int fp64, hipStream_t s) {
+hipError_t launch_mono_z(const MonoArgs& a, int set, int R, int fp64, hipStream_t s) {
   if (a.ny > 65535) return hipErrorInvalidValue;
-  return dispatch_r<RunZ>(R, a, fp64, s);
+  return dispatch_r<RunZ>(R, a, set, fp64, s);
 }
 
-hipError_t launch_carrier_xy(const CarrierArgs& a, int R, int fp64, hipStream_t s) {
-  return dispatch_r<RunXY>(R, a, fp64, s);
+hipError_t launch_mono_xy(const MonoArgs& a, int set, int R, int fp64, hipStream_t s) {
+  return dispatch_r<RunXY>(R, a, set, fp64, s);
 }
 
 }  // namespace kcf

@@ -65,6 +65,14 @@ class CarrierStats(C.Structure):
     as_dict = WidthStats.as_dict
 
 
+class Moment3Stats(C.Structure):
+    _fields_ = [("mean_m3", C.c_double * 10), ("rms_m3", C.c_double * 10),
+                ("mean_theta_t", C.c_double), ("n_points", C.c_int64), ("n_nonfinite", C.c_int64),
+                ("raw", C.c_double * 23)]
+
+    as_dict = WidthStats.as_dict
+
+
 class InputSummary(C.Structure):
     _fields_ = [("mean_rho", C.c_double), ("ek", C.c_double), ("enstrophy", C.c_double),
                 ("n_nonfinite", C.c_int64)]
@@ -91,6 +99,9 @@ _SIGS = {
                                    C.POINTER(Outputs), C.POINTER(WidthStats)]),
     "kcf_sgs_carrier": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.POINTER(Filter), C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(CarrierStats)]),
+    "kcf_sgs_moment3": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.POINTER(Filter), C.c_void_p,
+                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.POINTER(Moment3Stats)]),
     "kcf_input_stats": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p,
                                   C.POINTER(InputSummary)]),
     "kcf_reduce_check": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -273,6 +284,19 @@ class Context:
         st = CarrierStats() if stats else None
         check(self._lib.kcf_sgs_carrier(self.handle, C.byref(g), C.byref(fl), _ptr(rho), _ptr(u),
                                         _ptr(f_sgs), _ptr(f_h2), C.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def sgs_moment3(self, rho, u, h, filt, theta=None, m3=None, theta_t=None, stats=True):
+        """Third-order SGS moment of one filter (kind, n[, precision]): m3 is an optional
+        (10, nz, ny, nx) device float32 tensor, theta_t an optional (nz, ny, nx) one (needs
+        theta); returns the statistics dict or None."""
+        nz, ny, nx = rho.shape
+        g = Grid(nx, ny, nz, h)
+        fl = Filter(*filt) if len(filt) == 3 else Filter(filt[0], filt[1], 0)
+        st = Moment3Stats() if stats else None
+        check(self._lib.kcf_sgs_moment3(self.handle, C.byref(g), C.byref(fl), _ptr(rho), _ptr(u),
+                                        _ptr(theta), _ptr(m3), _ptr(theta_t),
+                                        C.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
     def input_stats(self, rho, u, h):

@@ -118,6 +118,17 @@ def workload_fields(name: str, device="cpu", n=None):
     return turbulence(device=device, **p)
 
 
+def workload_temperature(name: str, amp: float = 0.05, device="cpu", n=None):
+    """Temperature theta = 1 + amp s (float32, (n, n, n)) for a named workload: s is a
+    spectral scalar with the workload's spectrum and its own seed (scalar seed + 1000)."""
+    p = dict(WORKLOADS[name])
+    if n is not None:
+        p["k0"] = p["k0"] * n / p["n"]
+        p["n"] = n
+    s = spectral_scalar(p["n"], p["k0"], p["scal_seed"] + 1000, device)
+    return (1.0 + amp * s).to(torch.float32)
+
+
 def grid_coords(n: int, dtype=np.float64):
     """Coordinates X, Y, Z in [0, 2 pi) broadcast as (z, y, x)."""
     x = 2.0 * np.pi * np.arange(n, dtype=dtype) / n
