@@ -132,6 +132,29 @@ typedef struct {
                                    non-finite count */
 } kcf_moment3_stats;
 
+/* Parameters of the KC-MP evaluation (kcf_kc_mp). */
+typedef struct {
+  double nu;          /* molecular kinematic viscosity (>= 0), in the units of u and h */
+  double dt;          /* time step of the shifted relaxation time tau_hat = nu/theta + dt/2
+                         (>= 0; 0 = continuum) */
+  double theta;       /* reference temperature theta_R (> 0; c_s^2 in the units of u) */
+  double c_nu;        /* closure constant C_nu (the paper's KC-MP value is 0.035) */
+  int rho_ref_one;    /* 1: k_sgs = |m_aa| / 2 (operational reference density 1);
+                         0: |m_aa| / (2 rho_bar) */
+} kcf_kc_params;
+
+/* Statistics of the KC-MP evaluation against the exact tau, over the finite points. */
+typedef struct {
+  double corr[6];               /* Pearson r(m_sgs_c, tau_c), c = xx xy xz yy yz zz */
+  double rel_err;               /* (sum |m_sgs - tau|_F^2 / sum |tau|_F^2)^(1/2), all 9 pairs */
+  double mean_m[6], mean_tau[6];
+  double mean_k, mean_k_exact;  /* <k_sgs> from m_sgs and from tau */
+  double mean_omega, mean_omega_exact;  /* <omega_sgs> from m_sgs and from tau */
+  double clip, clip_exact;      /* fraction of points with nu_t_eff = nu */
+  int64_t n_points, n_nonfinite;
+  double raw[40];               /* the raw FP64 sums */
+} kcf_kc_stats;
+
 typedef struct {
   double mean_rho;              /* <rho> */
   double ek;                    /* <rho |u|^2 / 2> */
@@ -236,6 +259,27 @@ int kcf_sgs_carrier(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filter
 int kcf_sgs_moment3(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filter,
                     const float *rho, const float *u, const float *theta, float *m3,
                     float *theta_t, kcf_moment3_stats *stats);
+
+/* A priori evaluation of the KC-MP closure for one filter width (App. "Operational
+ * implementation of KC-MP", Sec. "Moment-Projected Closure (KC-MP)"). The fine-grained state
+ * is taken as f0(rho, u) plus its Chapman-Enskog part, whose second moment is
+ * -2 rho theta tau_hat S(u) (S from the central differences of eqs. fd and
+ * strain_rate_discrete); filtering it gives the coarse non-equilibrium moment
+ * m_cneq = tau - 2 theta tau_hat bar(rho S), and the closure's SGS moment is
+ *   m_sgs = m_cneq - m_CE = tau - 2 theta tau_hat (bar(rho S) - rho_bar S_t),
+ * m_CE = -2 rho_bar theta tau_hat S_t, S_t = S(ut) (eq. m_ce_reference and its operational
+ * form). From m_sgs, the relaxation-rate field of eq. omega_sgs_operational:
+ *   k_sgs = |m_sgs_aa| / (2 rho_ref), nu_t_eff = max(nu, C_nu Delta sqrt(k_sgs)),
+ *   omega_sgs = (nu_t_eff / theta + dt / 2)^-1     (Delta = the filter width),
+ * and the same rates from the exact tau for the statistics. Outputs (device, each may be
+ * NULL, but not all of them and stats): m_sgs [6][N] (xx xy xz yy yz zz), k_sgs, nu_t_eff,
+ * omega_sgs [N]. The call runs the filter path (kcf_filter_favre, into a context scratch of
+ * 16 N floats for rho_bar, tau and G), then filters rho S_ij in z slabs (two timed kernels
+ * per slab); with stats it synchronises.
+ * Errors: as kcf_sgs_carrier; KCF_EINVAL for a NULL or out-of-range kp. */
+int kcf_kc_mp(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filter, const float *rho,
+              const float *u, const kcf_kc_params *kp, float *m_sgs, float *k_sgs,
+              float *nu_t_eff, float *omega_sgs, kcf_kc_stats *stats);
 
 /* E_k, enstrophy and <rho> of the unfiltered input (synchronises). */
 int kcf_input_stats(kcf_ctx *ctx, const kcf_grid *grid, const float *rho, const float *u,

@@ -65,6 +65,45 @@ def kc_mp(rho, u, kind: int, n_delta: int, h: float, nu: float, dt: float = 0.0,
                 omega_exact=ome, tau_hat=tau_hat)
 
 
+def kc_mp_at(rho, u, kind: int, n_delta: int, h: float, nu: float, dt: float, theta: float,
+             c_nu: float, rho_ref_one, pts):
+    """m_sgs (npts, 3, 3), k_sgs, nu_t_eff, omega_sgs at points (k, j, i) by direct sums:
+    rho_bar, tau and G from fields.sampled_points, bar(rho S) from the strain of the
+    (2R+1)^3 neighbourhood (itself from the neighbours one cell further out)."""
+    w, R = F.filter_weights(kind, n_delta)
+    rho = np.asarray(rho)
+    u = np.asarray(u)
+    nz, ny, nx = rho.shape
+    sp = F.sampled_points(rho, u, kind, n_delta, h, pts)
+    w3 = np.einsum("a,b,c->abc", w, w, w)
+    offs = np.arange(-R - 1, R + 2)
+    tau_hat = nu / theta + 0.5 * dt
+    m_all, k_all, nue_all, om_all = [], [], [], []
+    for n, (k, j, i) in enumerate(np.asarray(pts).reshape(-1, 3)):
+        ix = np.ix_((k + offs) % nz, (j + offs) % ny, (i + offs) % nx)
+        r = rho[ix].astype(np.float64)
+        uu = np.stack([u[a][ix] for a in range(3)]).astype(np.float64)
+        G = np.empty((3, 3) + r.shape)
+        for a in range(3):
+            for b in range(3):
+                ax = F.AXIS[b]
+                G[a, b] = (np.roll(uu[a], -1, axis=ax) - np.roll(uu[a], 1, axis=ax)) / (2.0 * h)
+        S = 0.5 * (G + np.swapaxes(G, 0, 1))
+        inner = (slice(1, -1),) * 3
+        rs = np.array([[np.sum(w3 * (r * S[a, b])[inner]) for b in range(3)] for a in range(3)])
+        Gt = sp["G"][n]
+        St = 0.5 * (Gt + Gt.T)
+        rb = sp["rho_bar"][n]
+        m = sp["tau"][n] - 2.0 * theta * tau_hat * (rs - rb * St)
+        kk, nue, om = rates(m[..., None, None], np.array([rb]), n_delta * h, nu, dt, theta, c_nu,
+                            rho_ref_one)
+        m_all.append(m)
+        k_all.append(float(kk[0, 0]))
+        nue_all.append(float(nue[0, 0]))
+        om_all.append(float(om[0, 0]))
+    return np.array(m_all), np.array(k_all), np.array(nue_all), np.array(om_all)
+
+
 def kc_mp_stats(r, nu):
     """Comparison of the KC-MP estimate with the exact tau: Pearson r per stored component,
     relative Frobenius error, means of the rates and the fractions clipped to nu."""

@@ -22,7 +22,9 @@ struct kcf_ctx {
   void* d_xy = nullptr;        // slab buffer of the general-tap filter
   size_t xy_cap = 0;           // bytes
   float* d_fld = nullptr;      // Favre fields the caller did not ask for (10 N floats)
-  size_t fld_cap = 0;          // floats
+  size_t fld_cap = 0;          // bytes
+  float* d_kc = nullptr;       // rho_bar, tau and G for the KC-MP evaluation (16 N floats)
+  size_t kc_cap = 0;           // bytes
 };
 
 namespace {
@@ -272,9 +274,10 @@ int run_monomials(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, in
     return rc;
   A.zbuf = c->d_xy;
   int64_t nrec = 0;  // statistics records of all slabs
+  const int rpb = mono_records_per_block(set);
   for (int zs = 0; zs < grid->nz; zs += slab) {
     A.nzs = std::min(slab, grid->nz - zs);
-    nrec += mono_xy_records(A);
+    nrec += mono_xy_records(A) * rpb;
   }
   if (stats) {
     if (nrec > INT32_MAX) return fail(KCF_EUNSUPPORTED, "grid too large for statistics");
@@ -285,7 +288,7 @@ int run_monomials(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, in
     A.zs = zs;
     A.nzs = std::min(slab, grid->nz - zs);
     A.partials = stats ? c->d_part + (size_t)rec0 * nstat : nullptr;
-    rec0 += mono_xy_records(A);
+    rec0 += mono_xy_records(A) * rpb;
     if ((rc = timed_begin(c))) return rc;
     hipError_t e = launch_mono_z(A, set, R, fp64, c->stream);
     if (e != hipSuccess) return hip_fail(e, "z pass launch");
@@ -352,6 +355,7 @@ void kcf_ctx_destroy(kcf_ctx* c) {
   if (c->d_part) hipFree(c->d_part);
   if (c->d_xy) hipFree(c->d_xy);
   if (c->d_fld) hipFree(c->d_fld);
+  if (c->d_kc) hipFree(c->d_kc);
   if (c->d_sums) hipFree(c->d_sums);
   if (c->h_sums) hipHostFree(c->h_sums);
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
@@ -652,6 +656,75 @@ int kcf_sgs_moment3(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, 
         stats->rms_m3[k] = std::sqrt(raw[M3_SQ + k] / n);
       }
       stats->mean_theta_t = raw[M3_THETA] / n;
+    }
+  }
+  return KCF_OK;
+}
+
+int kcf_kc_mp(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, const float* rho,
+              const float* u, const kcf_kc_params* kp, float* m_sgs, float* k_sgs,
+              float* nu_t_eff, float* omega_sgs, kcf_kc_stats* stats) {
+  if (!c) return fail(KCF_EINVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!filter || !rho || !u || !kp) return fail(KCF_EINVAL, "NULL argument");
+  if (!m_sgs && !k_sgs && !nu_t_eff && !omega_sgs && !stats)
+    return fail(KCF_EINVAL, "nothing requested");
+  if (!(kp->nu >= 0) || !(kp->dt >= 0) || !(kp->theta > 0) || !(kp->c_nu >= 0) ||
+      (kp->rho_ref_one != 0 && kp->rho_ref_one != 1))
+    return fail(KCF_EINVAL, "KC parameters: nu, dt, c_nu >= 0, theta > 0, rho_ref_one 0 or 1");
+  const int64_t N = (int64_t)grid->nx * grid->ny * grid->nz;
+  // rho_bar, tau and G of the filter path, held by the context
+  if ((rc = ensure_buffer(c, c->d_kc, c->kc_cap, sizeof(float) * 16 * (size_t)N,
+                          "cannot allocate the KC field scratch")))
+    return rc;
+  kcf_outputs o;
+  std::memset(&o, 0, sizeof(o));
+  o.rho_bar = c->d_kc;
+  o.tau = c->d_kc + N;
+  o.grad = c->d_kc + 7 * N;
+  if ((rc = kcf_filter_favre(c, grid, filter, 1, rho, u, &o, nullptr, nullptr))) return rc;
+  MonoArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.rho = rho;
+  A.u = u;
+  A.ext = c->d_kc;
+  A.m_sgs = m_sgs;
+  A.k_sgs = k_sgs;
+  A.nu_t_eff = nu_t_eff;
+  A.omega_sgs = omega_sgs;
+  const double tau_hat = kp->nu / kp->theta + 0.5 * kp->dt;
+  A.inv2h = (float)(1.0 / (2.0 * grid->h));
+  A.kc_coef = (float)(2.0 * kp->theta * tau_hat);
+  A.nu = (float)kp->nu;
+  A.inv_theta = (float)(1.0 / kp->theta);
+  A.half_dt = (float)(0.5 * kp->dt);
+  A.cnu_delta = (float)(kp->c_nu * filter->delta_over_h * grid->h);
+  A.rho_ref_one = kp->rho_ref_one;
+  if ((rc = run_monomials(c, grid, filter, kSetKcMp, 6, kKcStat, A, stats != nullptr))) return rc;
+  if (stats) {
+    const double* raw = c->h_sums;
+    std::memset(stats, 0, sizeof(*stats));
+    std::memcpy(stats->raw, raw, sizeof(double) * kKcStat);
+    const double n = raw[KC_N];
+    stats->n_points = (int64_t)llround(n);
+    stats->n_nonfinite = (int64_t)llround(raw[KC_NONFINITE]);
+    if (n > 0) {
+      for (int k = 0; k < 6; ++k) {
+        const double sm = raw[KC_M + k], st = raw[KC_T + k];
+        const double cov = raw[KC_MT + k] - sm * st / n;
+        const double vm = raw[KC_M2 + k] - sm * sm / n, vt = raw[KC_T2 + k] - st * st / n;
+        stats->corr[k] = (vm > 0 && vt > 0) ? cov / std::sqrt(vm * vt) : NAN;
+        stats->mean_m[k] = sm / n;
+        stats->mean_tau[k] = st / n;
+      }
+      stats->rel_err = raw[KC_TAU2] > 0 ? std::sqrt(raw[KC_ERR2] / raw[KC_TAU2]) : NAN;
+      stats->mean_k = raw[KC_K] / n;
+      stats->mean_k_exact = raw[KC_KE] / n;
+      stats->mean_omega = raw[KC_OM] / n;
+      stats->mean_omega_exact = raw[KC_OME] / n;
+      stats->clip = raw[KC_CLIP] / n;
+      stats->clip_exact = raw[KC_CLIPE] / n;
     }
   }
   return KCF_OK;

@@ -208,14 +208,20 @@ __device__ __forceinline__ double swap_add(double x, double y) {
 }
 
 // Slots are folded in the order k, k + 20 (first swap) and k, k + 10 (second swap), one
-// accumulator at a time, so that only a few contributions are live at once.
-__device__ __forceinline__ void stat_add(const StatIn& I, StatAcc& a) {
+// accumulator at a time, so that only a few contributions are live at once. val(s) gives
+// slot s (0..39) of the lane's point.
+template <class V>
+__device__ __forceinline__ void stat_fold(const V& val, StatAcc& a) {
 #pragma unroll
   for (int k = 0; k < 10; ++k) {
-    const double lo = swap_add<32>(stat_val(I, k), stat_val(I, k + 20));
-    const double hi = swap_add<32>(stat_val(I, k + 10), stat_val(I, k + 30));
+    const double lo = swap_add<32>(val(k), val(k + 20));
+    const double hi = swap_add<32>(val(k + 10), val(k + 30));
     a.s[k] += swap_add<16>(lo, hi);
   }
+}
+
+__device__ __forceinline__ void stat_add(const StatIn& I, StatAcc& a) {
+  stat_fold([&](int s) { return stat_val(I, s); }, a);
 }
 
 // Wave totals: the 16-lane reduction of every accumulator, then lanes 0, 16, 32 and 48

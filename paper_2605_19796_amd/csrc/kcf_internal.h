@@ -105,11 +105,16 @@ hipError_t launch_taps(const TapArgs& a, int R, int fp64, hipStream_t s);
 
 // Filtered monomials of rho u (and rho theta): the SGS carrier of the D3Q27 lattice and the
 // third-order SGS moment (kcf_monomials.hip)
-constexpr int kSetCarrier = 0, kSetMoment3 = 1;
+constexpr int kSetCarrier = 0, kSetMoment3 = 1, kSetKcMp = 2;
 constexpr int kCStat = 9;   // FP64 sums of the carrier
 enum CarrierSlot { C_N = 0, C_F2 = 1, C_ERR2 = 2, C_HERM = 3, C_NONFINITE = 8 };
 constexpr int kM3Stat = 23;  // FP64 sums of the third-order moment
 enum Moment3Slot { M3_N = 0, M3_SUM = 1, M3_SQ = 11, M3_THETA = 21, M3_NONFINITE = 22 };
+constexpr int kKcStat = 40;  // FP64 sums of the KC-MP evaluation
+enum KcSlot {
+  KC_N = 0, KC_M = 1, KC_T = 7, KC_M2 = 13, KC_T2 = 19, KC_MT = 25, KC_ERR2 = 31, KC_TAU2 = 32,
+  KC_K = 33, KC_KE = 34, KC_OM = 35, KC_OME = 36, KC_CLIP = 37, KC_CLIPE = 38, KC_NONFINITE = 39
+};
 
 struct MonoArgs {
   const float* rho;
@@ -127,12 +132,26 @@ struct MonoArgs {
   float* f_h2;             // carrier: [27][N], or NULL
   float* m3;               // third-order moment: [10][N], or NULL
   float* theta_t;          // Favre temperature: [N], or NULL
-  double* partials;        // [mono_xy_records][statistics] records of the slab, or NULL
+  // KC-MP evaluation
+  const float* ext;        // stored filtered fields: rho_bar [N], tau [6N], G [9N]
+  float* m_sgs;            // [6][N], or NULL
+  float* k_sgs;            // [N], or NULL
+  float* nu_t_eff;         // [N], or NULL
+  float* omega_sgs;        // [N], or NULL
+  float inv2h;             // 1 / (2 h)
+  float kc_coef;           // 2 theta tau_hat
+  float nu;                // molecular viscosity
+  float inv_theta;         // 1 / theta
+  float half_dt;           // dt / 2
+  float cnu_delta;         // C_nu Delta
+  int rho_ref_one;         // k_sgs with rho_0 = 1 (1) or rho_bar (0)
+  double* partials;        // [mono_records][statistics] records of the slab, or NULL
 };
 int mono_tile_x();                  // the x-y tile
 int mono_tile_y();
 int mono_z_planes(int fp64);        // planes per thread of the z pass
-int64_t mono_xy_records(const MonoArgs& a);  // statistics records of one slab
+int64_t mono_xy_records(const MonoArgs& a);  // x-y workgroups of one slab
+int mono_records_per_block(int set);         // statistics records per x-y workgroup
 hipError_t launch_mono_z(const MonoArgs& a, int set, int R, int fp64, hipStream_t s);
 hipError_t launch_mono_xy(const MonoArgs& a, int set, int R, int fp64, hipStream_t s);
 

@@ -7,7 +7,10 @@
 //            closure from tau (eq. f_sgs_KCMP);
 //   moment3  the third-order SGS moment m3_ijk = bar(rho u_i u_j u_k) - rho_bar ut_i ut_j ut_k
 //            (the order-3 term of eq. f_sgs_hermite) and the Favre temperature
-//            bar(rho theta) / rho_bar (definition after eq. f0resolved).
+//            bar(rho theta) / rho_bar (definition after eq. f0resolved);
+//   kc-mp    bar(rho S_ij) of the input strain, for the a priori KC-MP estimate of the SGS
+//            second moment and the KC relaxation-rate field (App. "Operational
+//            implementation of KC-MP", eq. omega_sgs_operational).
 //
 // Carrier. With velocities in units of sqrt(theta_R) and xh = xi / sqrt(theta_R) in
 // {0, +-sqrt3}, the equilibrium is w_i rho prod_a (P_0 + P_1(xh_ia) u_a + P_2(xh_ia) u_a^2)
@@ -55,6 +58,38 @@ template <>
 __device__ __forceinline__ const float* cweights<float>(const MonoArgs& A) { return A.w; }
 template <>
 __device__ __forceinline__ const double* cweights<double>(const MonoArgs& A) { return A.wd; }
+
+// Statistics of the carrier and third-order sets: NS FP64 sums per thread over its points,
+// reduced over the wave and the workgroup in a fixed order into one record per workgroup.
+template <int NS>
+struct ArrayAcc {
+  double v[NS];
+  static constexpr int kRecords = 1;
+  __device__ void zero() {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) v[k] = 0.0;
+  }
+  // every thread of the workgroup calls this
+  __device__ void write(double* part, double* smem, int item) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) v[k] += __shfl_xor(v[k], d);
+    }
+    if (__lane_id() == 0) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) smem[(tid >> 6) * NS + k] = v[k];
+    }
+    __syncthreads();
+    if (tid < NS) {
+      double a = 0;
+#pragma unroll
+      for (int wv = 0; wv < kXT / 64; ++wv) a += smem[wv * NS + tid];
+      part[(int64_t)item * NS + tid] = a;
+    }
+  }
+};
 
 // ---------------------------------------------------------------- the SGS carrier
 // Monomial m = a + 3 b + 9 c stands for rho u_x^a u_y^b u_z^c.
@@ -112,9 +147,11 @@ struct CarrierSet {
     }
   }
 
+  using Acc = ArrayAcc<kStat>;
+
   template <typename T>
   __device__ static void epilogue(const MonoArgs& A, const T (&M)[kQ], bool valid, int64_t g,
-                                  double (&acc)[kStat]) {
+                                  Acc& acc) {
     const T rb = M[0];
     const T ri = (T)1 / rb;
     const T uv[3] = {M[1] * ri, M[3] * ri, M[9] * ri};
@@ -172,12 +209,12 @@ struct CarrierSet {
     }
     const bool finite = isfinite(sf2 + serr + herm[0] + herm[1] + herm[2] + herm[3] + herm[4]);
     const bool use = valid && finite;
-    acc[C_N] += use ? 1.0 : 0.0;
-    acc[C_F2] += use ? (double)sf2 : 0.0;
-    acc[C_ERR2] += use ? (double)serr : 0.0;
+    acc.v[C_N] += use ? 1.0 : 0.0;
+    acc.v[C_F2] += use ? (double)sf2 : 0.0;
+    acc.v[C_ERR2] += use ? (double)serr : 0.0;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) acc[C_HERM + k] += use ? (double)herm[k] : 0.0;
-    acc[C_NONFINITE] += valid && !finite ? 1.0 : 0.0;
+    for (int k = 0; k < 5; ++k) acc.v[C_HERM + k] += use ? (double)herm[k] : 0.0;
+    acc.v[C_NONFINITE] += valid && !finite ? 1.0 : 0.0;
   }
 };
 
@@ -218,9 +255,11 @@ struct Moment3Set {
     }
   }
 
+  using Acc = ArrayAcc<kStat>;
+
   template <typename T>
   __device__ static void epilogue(const MonoArgs& A, const T (&M)[kQ], bool valid, int64_t g,
-                                  double (&acc)[kStat]) {
+                                  Acc& acc) {
     const T rb = M[0];
     const T ri = (T)1 / rb;
     const T uv[3] = {M[1] * ri, M[2] * ri, M[3] * ri};
@@ -244,14 +283,111 @@ struct Moment3Set {
     }
     const bool finite = isfinite(s + tt);
     const bool use = valid && finite;
-    acc[M3_N] += use ? 1.0 : 0.0;
+    acc.v[M3_N] += use ? 1.0 : 0.0;
 #pragma unroll
     for (int c = 0; c < 10; ++c) {
-      acc[M3_SUM + c] += use ? (double)m3[c] : 0.0;
-      acc[M3_SQ + c] += use ? (double)(m3[c] * m3[c]) : 0.0;
+      acc.v[M3_SUM + c] += use ? (double)m3[c] : 0.0;
+      acc.v[M3_SQ + c] += use ? (double)(m3[c] * m3[c]) : 0.0;
     }
-    acc[M3_THETA] += use ? (double)tt : 0.0;
-    acc[M3_NONFINITE] += valid && !finite ? 1.0 : 0.0;
+    acc.v[M3_THETA] += use ? (double)tt : 0.0;
+    acc.v[M3_NONFINITE] += valid && !finite ? 1.0 : 0.0;
+  }
+};
+
+// ---------------------------------------------------------------- a priori KC-MP
+// Quantities: rho S_ij of the input (S from central differences, stored order xx xy xz yy yz
+// zz). The z pass is k_kc_z (it needs the neighbours of each point); the epilogue reads the
+// stored rho_bar, tau and G of the filter path at its point and forms
+//   m_sgs = tau - 2 theta tau_hat (bar(rho S) - rho_bar S_t),   S_t = (G + G^T) / 2,
+// the KC-MP estimate of the SGS second moment when the fine-grained state carries its
+// Chapman-Enskog part (m_cneq - m_CE, eqs. m_ce_reference and kcmp_operational_msgstrace),
+// and the rates of eq. omega_sgs_operational from it and from the exact tau.
+struct KcSet {
+  static constexpr int kQ = 6;
+  static constexpr int kStat = kKcStat;
+  static constexpr bool kOptionalLast = false;
+
+  // 40 FP64 sums folded over the wave (the filter path's statistics scheme), one record per
+  // wave
+  struct Acc {
+    StatAcc a;
+    static constexpr int kRecords = kXT / 64;
+    __device__ void zero() { stat_zero(a); }
+    __device__ void write(double* part, double*, int item) {
+      write_stats(part + ((int64_t)item * kRecords + (threadIdx.x >> 6)) * kKcStat, a);
+    }
+  };
+
+  __device__ static void rates(const MonoArgs& A, float tr, float rb, float& k, float& nue,
+                               float& om, bool& clip) {
+    k = fabsf(tr) / (2.f * (A.rho_ref_one ? 1.f : rb));
+    const float nut = A.cnu_delta * sqrtf(k);
+    clip = !(nut > A.nu);
+    nue = clip ? A.nu : nut;
+    om = 1.f / (nue * A.inv_theta + A.half_dt);
+  }
+
+  template <typename T>
+  __device__ static void epilogue(const MonoArgs& A, const T (&M)[kQ], bool valid, int64_t g,
+                                  Acc& acc) {
+    const int64_t N = A.ntot;
+    const int64_t gc = valid ? g : 0;  // points past the grid edge read a valid point
+    const float rb = A.ext[gc];
+    float tau[6], G[9];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tau[c] = A.ext[(1 + c) * N + gc];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) G[c] = A.ext[(7 + c) * N + gc];
+    const float St[6] = {G[0], 0.5f * (G[1] + G[3]), 0.5f * (G[2] + G[6]), G[4],
+                         0.5f * (G[5] + G[7]), G[8]};
+    float m[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const float d = (float)(M[c] - (T)rb * (T)St[c]);  // bar(rho S) - rho_bar S_t
+      m[c] = fmaf(-A.kc_coef, d, tau[c]);
+    }
+    float k, nue, om, ke, nuee, ome;
+    bool clip, clipe;
+    rates(A, m[0] + m[3] + m[5], rb, k, nue, om, clip);
+    rates(A, tau[0] + tau[3] + tau[5], rb, ke, nuee, ome, clipe);
+    if (valid) {
+      if (A.m_sgs) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) A.m_sgs[c * N + g] = m[c];
+      }
+      if (A.k_sgs) A.k_sgs[g] = k;
+      if (A.nu_t_eff) A.nu_t_eff[g] = nue;
+      if (A.omega_sgs) A.omega_sgs[g] = om;
+    }
+    float err = 0.f, nrm = 0.f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const float wgt = (c == 0 || c == 3 || c == 5) ? 1.f : 2.f;  // off-diagonal pairs twice
+      const float e = m[c] - tau[c];
+      err = fmaf(wgt * e, e, err);
+      nrm = fmaf(wgt * tau[c], tau[c], nrm);
+    }
+    const bool finite = isfinite(err + nrm + k + om + ke + ome);
+    const bool use = valid && finite;
+    auto val = [&](int s) -> double {
+      if (s == KC_NONFINITE) return valid && !finite ? 1.0 : 0.0;
+      if (!use) return 0.0;
+      if (s == KC_N) return 1.0;
+      if (s >= KC_M && s < KC_M + 6) return (double)m[s - KC_M];
+      if (s >= KC_T && s < KC_T + 6) return (double)tau[s - KC_T];
+      if (s >= KC_M2 && s < KC_M2 + 6) return (double)m[s - KC_M2] * (double)m[s - KC_M2];
+      if (s >= KC_T2 && s < KC_T2 + 6) return (double)tau[s - KC_T2] * (double)tau[s - KC_T2];
+      if (s >= KC_MT && s < KC_MT + 6) return (double)m[s - KC_MT] * (double)tau[s - KC_MT];
+      if (s == KC_ERR2) return (double)err;
+      if (s == KC_TAU2) return (double)nrm;
+      if (s == KC_K) return (double)k;
+      if (s == KC_KE) return (double)ke;
+      if (s == KC_OM) return (double)om;
+      if (s == KC_OME) return (double)ome;
+      if (s == KC_CLIP) return clip ? 1.0 : 0.0;
+      return clipe ? 1.0 : 0.0;  // KC_CLIPE
+    };
+    stat_fold(val, acc.a);
   }
 };
 
@@ -353,6 +489,108 @@ __device__ __forceinline__ void z_pass(const MonoArgs& A) {
   }
 }
 
+// z pass of the KC-MP set: rho S_ij at every window plane, S from central differences of
+// the input velocity (x and y neighbours read at the plane, z neighbours from the column).
+// The values of a plane are loaded two planes ahead of their use.
+struct KcPlane {
+  float r, c[3], xp[3], xm[3], yp[3], ym[3];  // rho; u at the column and its neighbours
+};
+
+template <int R, typename T>
+__device__ __forceinline__ void z_pass_kc(const MonoArgs& A) {
+  constexpr int ZT = cz_planes<T>();
+  constexpr int NJ = ZT + 2 * R;  // window planes z0 - R .. z0 + ZT + R - 1
+  const int x = blockIdx.x * kZB + threadIdx.x;
+  if (x >= A.nx) return;
+  const int y = blockIdx.y;
+  const int zl0 = blockIdx.z * ZT;
+  const int nk = min(ZT, A.nzs - zl0);
+  const int64_t plane = (int64_t)A.nx * A.ny;
+  const int64_t qstride = (int64_t)A.nzs * plane;
+  const int64_t nb = A.ntot * (int64_t)sizeof(float);
+  // byte offsets within a plane (< 2^32): the column and its four neighbours
+  const uint32_t c0 = (uint32_t)(y * A.nx + x) * 4u;
+  const uint32_t cxm = (uint32_t)(y * A.nx + wrapi(x - 1, A.nx)) * 4u;
+  const uint32_t cxp = (uint32_t)(y * A.nx + wrapi(x + 1, A.nx)) * 4u;
+  const uint32_t cym = (uint32_t)(wrapi(y - 1, A.ny) * A.nx + x) * 4u;
+  const uint32_t cyp = (uint32_t)(wrapi(y + 1, A.ny) * A.nx + x) * 4u;
+  const T* w = cweights<T>(A);
+  const T i2h = (T)A.inv2h;
+  auto load = [&](int zz, KcPlane& P) {
+    const char* pr = reinterpret_cast<const char*>(A.rho + (int64_t)zz * plane);
+    const char* pu = reinterpret_cast<const char*>(A.u + (int64_t)zz * plane);
+    P.r = *reinterpret_cast<const float*>(pr + c0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const char* q = pu + i * nb;
+      P.c[i] = *reinterpret_cast<const float*>(q + c0);
+      P.xp[i] = *reinterpret_cast<const float*>(q + cxp);
+      P.xm[i] = *reinterpret_cast<const float*>(q + cxm);
+      P.yp[i] = *reinterpret_cast<const float*>(q + cyp);
+      P.ym[i] = *reinterpret_cast<const float*>(q + cym);
+    }
+  };
+  T acc[6][ZT];
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+#pragma unroll
+    for (int k = 0; k < ZT; ++k) acc[q][k] = (T)0;
+  // planes j - 1, j, j + 1 in Pm, P0, Pp (shifted along, so that no array is indexed by j)
+  int zz = wrapi(A.zs + zl0 - R - 1, A.nz);
+  __asm__ volatile("" : "+s"(zz));
+  KcPlane Pm, P0, Pp, Pn;
+  load(zz, Pm);
+  zz = zz + 1 == A.nz ? 0 : zz + 1;
+  load(zz, P0);
+  zz = zz + 1 == A.nz ? 0 : zz + 1;
+  load(zz, Pp);
+  zz = zz + 1 == A.nz ? 0 : zz + 1;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    T G[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      G[i][0] = ((T)P0.xp[i] - (T)P0.xm[i]) * i2h;
+      G[i][1] = ((T)P0.yp[i] - (T)P0.ym[i]) * i2h;
+      G[i][2] = ((T)Pp.c[i] - (T)Pm.c[i]) * i2h;
+    }
+    const T r = (T)P0.r;
+    if (j + 2 <= NJ) {  // plane j + 2
+      load(zz, Pn);
+      zz = zz + 1 == A.nz ? 0 : zz + 1;
+    }
+    // keep the later loads below this point: the window is not held in registers
+    __builtin_amdgcn_sched_barrier(0);
+    const T p[6] = {r * G[0][0], r * ((T)0.5 * (G[0][1] + G[1][0])),
+                    r * ((T)0.5 * (G[0][2] + G[2][0])), r * G[1][1],
+                    r * ((T)0.5 * (G[1][2] + G[2][1])), r * G[2][2]};
+#pragma unroll
+    for (int k = 0; k < ZT; ++k) {
+      const int t = j - k;
+      if (t >= 0 && t <= 2 * R) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          acc[q][k] = fma(w[t], p[q], acc[q][k]);
+          // finish this plane's FMAs here: otherwise the products of every plane are kept
+          // live to form each output's sum in one chain
+          __asm__ volatile("" ::"v"(acc[q][k]));
+        }
+      }
+    }
+    Pm = P0;
+    P0 = Pp;
+    Pp = Pn;
+  }
+  T* out = reinterpret_cast<T*>(A.zbuf) + (int64_t)zl0 * plane + (int64_t)y * A.nx + x;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    T* o = out + (int64_t)q * qstride;
+#pragma unroll
+    for (int k = 0; k < ZT; ++k)
+      if (k < nk) o[(int64_t)k * plane] = acc[q][k];
+  }
+}
+
 template <int R, typename T, int NQ>
 struct XyLds {
   static constexpr int HX = kTX + 2 * R;
@@ -388,9 +626,8 @@ __device__ __forceinline__ void xy_pass(const MonoArgs& A) {
   const int64_t qstride = (int64_t)A.nzs * plane;
   const T* w = cweights<T>(A);
   const bool valid = x0 + px < A.nx && y0 + py < A.ny;
-  double acc[NS];  // this thread's FP64 sums over its points
-#pragma unroll
-  for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+  typename S::Acc acc;  // this thread's FP64 sums over its points
+  acc.zero();
   const int z_hi = min((zc + 1) * kXZ, A.nzs);
   for (int zl = zc * kXZ; zl < z_hi; ++zl) {
     const T* zb = reinterpret_cast<const T*>(A.zbuf) + (int64_t)zl * plane;
@@ -436,24 +673,7 @@ __device__ __forceinline__ void xy_pass(const MonoArgs& A) {
     const int64_t g = (int64_t)(A.zs + zl) * plane + (int64_t)(y0 + py) * A.nx + x0 + px;
     S::epilogue(A, M, valid, g, acc);
   }
-  if (!A.partials) return;
-  // ---- fixed-order wave and block reduction, one record per workgroup
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) acc[k] += __shfl_xor(acc[k], d);
-  }
-  if (__lane_id() == 0) {
-#pragma unroll
-    for (int k = 0; k < NS; ++k) smem[(tid >> 6) * NS + k] = acc[k];
-  }
-  __syncthreads();
-  if (tid < NS) {
-    double a = 0;
-#pragma unroll
-    for (int wv = 0; wv < kXT / 64; ++wv) a += smem[wv * NS + tid];
-    A.partials[(int64_t)item * NS + tid] = a;
-  }
+  if (A.partials) acc.write(A.partials, smem, item);
 }
 
 // Two waves per SIMD for the z kernels: the register budget then bounds how far the
@@ -480,6 +700,17 @@ __global__ void __launch_bounds__(kXT) k_moment3_xy(MonoArgs A) {
   xy_pass<Moment3Set, R, T>(A);
 }
 
+template <int R, typename T>
+__global__ void __launch_bounds__(kZB) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_kc_z(MonoArgs A) {
+  z_pass_kc<R, T>(A);
+}
+
+template <int R, typename T>
+__global__ void __launch_bounds__(kXT) k_kc_xy(MonoArgs A) {
+  xy_pass<KcSet, R, T>(A);
+}
+
 // ---------------------------------------------------------------- launches
 template <int R>
 hipError_t launch_z_of(const MonoArgs& a, int set, int fp64, hipStream_t s) {
@@ -490,6 +721,11 @@ hipError_t launch_z_of(const MonoArgs& a, int set, int fp64, hipStream_t s) {
       hipLaunchKernelGGL((k_carrier_z<R, double>), grid, dim3(kZB), 0, s, a);
     else
       hipLaunchKernelGGL((k_carrier_z<R, float>), grid, dim3(kZB), 0, s, a);
+  } else if (set == kSetKcMp) {
+    if (fp64)
+      hipLaunchKernelGGL((k_kc_z<R, double>), grid, dim3(kZB), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_kc_z<R, float>), grid, dim3(kZB), 0, s, a);
   } else {
     if (fp64)
       hipLaunchKernelGGL((k_moment3_z<R, double>), grid, dim3(kZB), 0, s, a);
@@ -508,6 +744,11 @@ hipError_t launch_xy_of(const MonoArgs& a, int set, int fp64, hipStream_t s) {
       hipLaunchKernelGGL((k_carrier_xy<R, double>), grid, dim3(kXT), 0, s, a);
     else
       hipLaunchKernelGGL((k_carrier_xy<R, float>), grid, dim3(kXT), 0, s, a);
+  } else if (set == kSetKcMp) {
+    if (fp64)
+      hipLaunchKernelGGL((k_kc_xy<R, double>), grid, dim3(kXT), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_kc_xy<R, float>), grid, dim3(kXT), 0, s, a);
   } else {
     if (fp64)
       hipLaunchKernelGGL((k_moment3_xy<R, double>), grid, dim3(kXT), 0, s, a);
@@ -556,6 +797,9 @@ int mono_tile_y() { return kTY; }
 int mono_z_planes(int fp64) { return fp64 ? cz_planes<double>() : cz_planes<float>(); }
 int64_t mono_xy_records(const MonoArgs& a) {
   return (int64_t)a.ntiles * ((a.nzs + kXZ - 1) / kXZ);
+}
+int mono_records_per_block(int set) {
+  return set == kSetKcMp ? KcSet::Acc::kRecords : 1;
 }
 
 hipError_t launch_mono_z(const MonoArgs& a, int set, int R, int fp64, hipStream_t s) {

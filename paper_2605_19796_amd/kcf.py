@@ -73,6 +73,21 @@ class Moment3Stats(C.Structure):
     as_dict = WidthStats.as_dict
 
 
+class KcParams(C.Structure):
+    _fields_ = [("nu", C.c_double), ("dt", C.c_double), ("theta", C.c_double),
+                ("c_nu", C.c_double), ("rho_ref_one", C.c_int)]
+
+
+class KcStats(C.Structure):
+    _fields_ = [("corr", C.c_double * 6), ("rel_err", C.c_double), ("mean_m", C.c_double * 6),
+                ("mean_tau", C.c_double * 6), ("mean_k", C.c_double), ("mean_k_exact", C.c_double),
+                ("mean_omega", C.c_double), ("mean_omega_exact", C.c_double),
+                ("clip", C.c_double), ("clip_exact", C.c_double), ("n_points", C.c_int64),
+                ("n_nonfinite", C.c_int64), ("raw", C.c_double * 40)]
+
+    as_dict = WidthStats.as_dict
+
+
 class InputSummary(C.Structure):
     _fields_ = [("mean_rho", C.c_double), ("ek", C.c_double), ("enstrophy", C.c_double),
                 ("n_nonfinite", C.c_int64)]
@@ -102,6 +117,9 @@ _SIGS = {
     "kcf_sgs_moment3": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.POINTER(Filter), C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.POINTER(Moment3Stats)]),
+    "kcf_kc_mp": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.POINTER(Filter), C.c_void_p,
+                            C.c_void_p, C.POINTER(KcParams), C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.POINTER(KcStats)]),
     "kcf_input_stats": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p,
                                   C.POINTER(InputSummary)]),
     "kcf_reduce_check": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -297,6 +315,21 @@ class Context:
         check(self._lib.kcf_sgs_moment3(self.handle, C.byref(g), C.byref(fl), _ptr(rho), _ptr(u),
                                         _ptr(theta), _ptr(m3), _ptr(theta_t),
                                         C.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def kc_mp(self, rho, u, h, filt, nu, dt=0.0, theta=1.0, c_nu=0.035, rho_ref_one=1,
+              m_sgs=None, k_sgs=None, nu_t_eff=None, omega_sgs=None, stats=True):
+        """A priori KC-MP SGS moment and relaxation-rate field of one filter (kind, n[,
+        precision]); outputs are optional device float32 tensors ((6, nz, ny, nx) for m_sgs,
+        (nz, ny, nx) for the rates). Returns the statistics dict or None."""
+        nz, ny, nx = rho.shape
+        g = Grid(nx, ny, nz, h)
+        fl = Filter(*filt) if len(filt) == 3 else Filter(filt[0], filt[1], 0)
+        kp = KcParams(nu, dt, theta, c_nu, rho_ref_one)
+        st = KcStats() if stats else None
+        check(self._lib.kcf_kc_mp(self.handle, C.byref(g), C.byref(fl), _ptr(rho), _ptr(u),
+                                  C.byref(kp), _ptr(m_sgs), _ptr(k_sgs), _ptr(nu_t_eff),
+                                  _ptr(omega_sgs), C.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
     def input_stats(self, rho, u, h):

@@ -79,3 +79,17 @@ def test_exact_rates_match_the_closure_oracle():
     assert np.max(np.abs(cl["omega_t"] - r["omega_exact"])) < 1e-12 * np.max(r["omega_exact"])
     st = KC.kc_mp_stats(r, nu)
     assert 0.0 <= st["clip"] <= 1.0 and -1.0 <= min(st["corr"]) <= 1.0
+
+
+def test_pointwise_equals_field():
+    rho, u = synth.random_fields((11, 12, 13), seed=45, rho_amp=0.2)
+    h = 2 * np.pi / 13
+    args = dict(nu=0.003, dt=0.5, theta=0.7, c_nu=0.035, rho_ref_one=False)
+    r = KC.kc_mp(rho, u, F.BOX, 4, h, **args)
+    pts = np.array([(0, 0, 0), (10, 11, 12), (5, 6, 2)])
+    m, k, nue, om = KC.kc_mp_at(rho, u, F.BOX, 4, h, args["nu"], args["dt"], args["theta"],
+                                args["c_nu"], args["rho_ref_one"], pts)
+    for n, (a, b, c) in enumerate(pts):
+        assert np.max(np.abs(m[n] - r["m_sgs"][:, :, a, b, c])) < 1e-14
+        assert abs(k[n] - r["k_sgs"][a, b, c]) < 1e-14
+        assert abs(om[n] - r["omega_sgs"][a, b, c]) < 1e-10 * abs(om[n])
