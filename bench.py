@@ -19,8 +19,9 @@ stream it runs on.
 Further sections of the same line: `carrier`, the a priori D3Q27 SGS carrier (f_sgs and its
 second-order Hermite reconstruction, stored, with statistics) on the 512^3 field at box 4h
 and 8h and on the 256^3 Gaussian-8h field; `moment3`, the third-order SGS moment and the
-Favre temperature on the 512^3 field with a spectral temperature; `learned`, training and the
-learned-vs-plain race.
+Favre temperature on the 512^3 field with a spectral temperature; `kc_mp`, the a priori KC-MP
+SGS moment and relaxation-rate field against the exact tau on the 512^3 field; `learned`,
+training and the learned-vs-plain race.
 
 Profiling modes (for rocprofv3 runs): --profile-run times a few steps and skips the CPU
 baseline and the learned section; --copy-calibration runs only a plain device copy of known
@@ -275,6 +276,58 @@ def moment3_section(ctx, rho, u, args):
     return out
 
 
+KC_BYTES_PER_POINT = 16 + 9 * 4  # read rho, u; write m_sgs (6), k_sgs, nu_t_eff, omega_sgs
+# lattice units: spacing and time step 1, theta_R = 1/3, velocities u sqrt(theta_R) (the
+# field's Mach numbers), nu = 1e-4 (shifted rate 1/tau_hat ~ 1.9994)
+KC_PARAMS = dict(nu=1e-4, dt=1.0, theta=1.0 / 3.0, c_nu=0.035, rho_ref_one=1)
+
+
+def kc_section(ctx, rho, u, args):
+    """A priori KC-MP SGS moment and relaxation-rate field (all outputs stored, statistics
+    against the exact tau) on the 512^3 field in lattice units, box 4h (FP64 sums) and 8h
+    (FP32)."""
+    import torch
+    from paper_2605_19796_amd import kcf
+    n = rho.shape[0]
+    h = 1.0
+    u = (u * math.sqrt(KC_PARAMS["theta"])).contiguous()
+    m = torch.empty((6,) + tuple(rho.shape), dtype=torch.float32, device=rho.device)
+    k, nue, om = (torch.empty_like(rho) for _ in range(3))
+    out = {"params": KC_PARAMS, "units": "lattice (h = dt = 1, u = Mach sqrt(theta_R))"}
+    reps = 2 if args.profile_run else 5
+    for name, filt in (("box4h_512", (kcf.BOX, 4)), ("box8h_512", (kcf.BOX, 8))):
+        progress(f"kc-mp {name}")
+        call = lambda: ctx.kc_mp(rho, u, h, filt, m_sgs=m, k_sgs=k, nu_t_eff=nue, omega_sgs=om,
+                                 **KC_PARAMS)
+        st = call()
+        ctx.enable_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st = call()
+        t1 = time.perf_counter()
+        kt = ctx.kernel_times()
+        ctx.enable_timing(False)
+        per = len(kt) // reps  # filter launch, then z and x-y per slab
+        ms = (t1 - t0) * 1e3 / reps
+        pts = float(n) ** 3
+        out[name] = {
+            "grid": n, "width_h": filt[1], "ms_per_call": ms, "points_per_s": pts / (ms * 1e-3),
+            "kernel_ms": {"filter_path": sum(kt[0::per]) / reps,
+                          "k_kc_z": sum(sum(kt[i::per]) for i in range(1, per, 2)) / reps,
+                          "k_kc_xy": sum(sum(kt[i::per]) for i in range(2, per, 2)) / reps},
+            "bytes_per_point": KC_BYTES_PER_POINT,
+            "call_gbs": KC_BYTES_PER_POINT * pts / (ms * 1e-3) / 1e9,
+            "corr_m_tau": st["corr"], "rel_err": st["rel_err"],
+            "mean_k": st["mean_k"], "mean_k_exact": st["mean_k_exact"],
+            "mean_omega": st["mean_omega"], "mean_omega_exact": st["mean_omega_exact"],
+            "clip": st["clip"], "clip_exact": st["clip_exact"],
+        }
+    del m, k, nue, om, u
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration():
     """One plain device-to-device copy of COPY_BYTES, for scaling FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -296,7 +349,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-carrier", action="store_true",
-                    help="skip the carrier and third-order moment sections")
+                    help="skip the carrier, third-order moment and KC-MP sections")
     ap.add_argument("--profile-run", action="store_true",
                     help="a few steps only (no CPU baseline, no learned section)")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -397,6 +450,7 @@ def main():
     if not args.no_carrier:
         line["carrier"] = carrier_section(ctx, rho, u, args)
         line["moment3"] = moment3_section(ctx, rho, u, args)
+        line["kc_mp"] = kc_section(ctx, rho, u, args)
     if not args.no_learned:
         del rho, u
         torch.cuda.empty_cache()
