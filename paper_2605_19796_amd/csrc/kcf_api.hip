@@ -254,8 +254,8 @@ int run_monomials(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, in
   A.ny = grid->ny;
   A.nz = grid->nz;
   A.ntot = (int64_t)grid->nx * grid->ny * grid->nz;
-  A.ntx = (grid->nx + mono_tile_x() - 1) / mono_tile_x();
-  A.nty = (grid->ny + mono_tile_y() - 1) / mono_tile_y();
+  A.ntx = (grid->nx + mono_tile_x(R) - 1) / mono_tile_x(R);
+  A.nty = (grid->ny + mono_tile_y(R) - 1) / mono_tile_y(R);
   A.ntiles = A.ntx * A.nty;
   A.nq = nq;
   for (int m = 0; m < 2 * R + 1; ++m) {

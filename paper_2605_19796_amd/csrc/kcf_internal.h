@@ -147,8 +147,8 @@ struct MonoArgs {
   int rho_ref_one;         // k_sgs with rho_0 = 1 (1) or rho_bar (0)
   double* partials;        // [mono_records][statistics] records of the slab, or NULL
 };
-int mono_tile_x();                  // the x-y tile
-int mono_tile_y();
+int mono_tile_x(int R);             // the x-y tile for radius R
+int mono_tile_y(int R);
 int mono_z_planes(int fp64);        // planes per thread of the z pass
 int64_t mono_xy_records(const MonoArgs& a);  // x-y workgroups of one slab
 int mono_records_per_block(int set);         // statistics records per x-y workgroup

@@ -26,7 +26,7 @@
 //   k_*_z   one thread per (x, y) column and ZT planes: the set's products of the input,
 //           one group of up to nine at a time, filtered along z over a register window of
 //           the input planes and written to the slab buffer [quantities][planes][ny][nx];
-//   k_*_xy  one workgroup per (kTX x kTY tile, run of eight planes), XCD-banded: per plane,
+//   k_*_xy  one workgroup per (tile of 256 points, run of eight planes), XCD-banded: per plane,
 //           the quantities of the tile and its halo staged in LDS G at a time, filtered along
 //           x and y in place, each thread keeping its point's filtered values; then the set's
 //           epilogue (stores and statistics: a point's values in FP32, their sums over points
@@ -43,8 +43,6 @@ namespace {
 using namespace dev;
 
 constexpr int kZB = 256;  // threads of the z kernels
-constexpr int kTX = 16;   // tile of the x-y kernels: kTX x kTY points, one per thread
-constexpr int kTY = 16;
 constexpr int kXT = 256;  // threads of the x-y kernels (one per tile point)
 constexpr int kLook = 3;  // input planes in flight ahead of the FMAs in the z kernels
 constexpr int kXZ = 8;    // planes per workgroup of the x-y kernels
@@ -591,15 +589,25 @@ __device__ __forceinline__ void z_pass_kc(const MonoArgs& A) {
   }
 }
 
+// x-y tile of kXT points: 32 x 8 for narrow windows (full 128-byte rows in every store),
+// 16 x 16 for wide ones (smaller halo); the x pass works on 16-point row segments.
+template <int R>
+struct XyTile {
+  static constexpr int X = R <= 4 ? 32 : 16;
+  static constexpr int Y = kXT / X;
+  static constexpr int NH = X / 16;  // row segments
+};
+
 template <int R, typename T, int NQ>
 struct XyLds {
-  static constexpr int HX = kTX + 2 * R;
-  static constexpr int HY = kTY + 2 * R;
+  static constexpr int HX = XyTile<R>::X + 2 * R;
+  static constexpr int HY = XyTile<R>::Y + 2 * R;
   static constexpr int HXP = HX | 1;  // odd row stride
   static constexpr int NRAW = HX * HY;
   static constexpr int QS = HY * HXP;
-  // quantities per LDS round: nine while they fit in 64 KiB, else three
-  static constexpr int G = 9 * QS * (int)sizeof(T) <= 65536 ? 9 : 3;
+  // quantities per LDS round: nine while they fit in 68 KiB (two workgroups per CU), else
+  // three
+  static constexpr int G = 9 * QS * (int)sizeof(T) <= 69632 ? 9 : 3;
   static constexpr int doubles = (G * QS * (int)sizeof(T) + 7) / 8;
 };
 
@@ -607,6 +615,9 @@ template <class S, int R, typename T>
 __device__ __forceinline__ void xy_pass(const MonoArgs& A) {
   using L = XyLds<R, T, S::kQ>;
   constexpr int HX = L::HX, HY = L::HY, HXP = L::HXP, QS = L::QS, G = L::G;
+  constexpr int kTX = XyTile<R>::X, kTY = XyTile<R>::Y, NH = XyTile<R>::NH;
+  // LDS column of tile column x: the second row segment's x outputs sit 2R cells right
+  auto lcol = [](int x) { return x + (x >= 16 ? 2 * R : 0); };
   constexpr int NQ = S::kQ;
   constexpr int NS = S::kStat;
   static_assert(4 * NS <= L::doubles, "statistics records do not fit the LDS buffer");
@@ -645,19 +656,22 @@ __device__ __forceinline__ void xy_pass(const MonoArgs& A) {
           if (g0 + q < NQ && q < ng) d[q * QS] = zb[(int64_t)(g0 + q) * qstride + o];
       }
       __syncthreads();
-      // x, in place: one (quantity, row) per task
-      for (int t = tid; t < ng * HY; t += kXT) {
-        T* v = buf + t * HXP;
-        T vr[HX];
+      // x, in place: one (quantity, row, 16-point segment) per task; the second segment's
+      // outputs go 2R cells to the right, clear of the first segment's inputs
+      for (int t = tid; t < ng * HY * NH; t += kXT) {
+        const int h = t % NH;
+        T* v = buf + (t / NH) * HXP + h * 16;
+        T vr[16 + 2 * R];
 #pragma unroll
-        for (int i = 0; i < HX; ++i) vr[i] = v[i];
+        for (int i = 0; i < 16 + 2 * R; ++i) vr[i] = v[i];
+        T* vo = v + h * 2 * R;
 #pragma unroll
-        for (int o = 0; o < kTX; ++o) v[o] = tap_sum<R, T>(w, vr, o + R);
+        for (int o = 0; o < 16; ++o) vo[o] = tap_sum<R, T>(w, vr, o + R);
       }
       __syncthreads();
       // y, in place: one (quantity, column) per task, outputs to rows 0 .. kTY - 1
       for (int t = tid; t < ng * kTX; t += kXT) {
-        T* v = buf + (t / kTX) * QS + t % kTX;
+        T* v = buf + (t / kTX) * QS + lcol(t % kTX);
         T vr[HY];
 #pragma unroll
         for (int i = 0; i < HY; ++i) vr[i] = v[i * HXP];
@@ -667,7 +681,7 @@ __device__ __forceinline__ void xy_pass(const MonoArgs& A) {
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < G; ++q)
-        if (g0 + q < NQ) M[g0 + q] = q < ng ? buf[q * QS + py * HXP + px] : (T)0;
+        if (g0 + q < NQ) M[g0 + q] = q < ng ? buf[q * QS + py * HXP + lcol(px)] : (T)0;
       __syncthreads();
     }
     const int64_t g = (int64_t)(A.zs + zl) * plane + (int64_t)(y0 + py) * A.nx + x0 + px;
@@ -792,8 +806,8 @@ struct RunXY {
 
 }  // namespace
 
-int mono_tile_x() { return kTX; }
-int mono_tile_y() { return kTY; }
+int mono_tile_x(int R) { return R <= 4 ? XyTile<1>::X : XyTile<kMaxR>::X; }
+int mono_tile_y(int R) { return kXT / mono_tile_x(R); }
 int mono_z_planes(int fp64) { return fp64 ? cz_planes<double>() : cz_planes<float>(); }
 int64_t mono_xy_records(const MonoArgs& a) {
   return (int64_t)a.ntiles * ((a.nzs + kXZ - 1) / kXZ);
