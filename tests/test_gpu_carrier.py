@@ -83,6 +83,8 @@ CASES = [
     ("gauss4_fp32", (30, 33, 40), (F.GAUSS, 4, 1)),  # FP32, R = 6
     ("gauss8_fp32", (28, 36, 40), (F.GAUSS, 8, 1)),  # FP32, R = 12 (the Gaussian 8h taps)
     ("gauss8_fp64", (26, 26, 25), (F.GAUSS, 8, 2)),  # FP64, R = 12: three monomials per round
+    ("tiny_box4", (5, 6, 7), (F.BOX, 4, 0)),          # 2R + 1 = n along z, one partial tile
+    ("thin_box2", (3, 70, 3), (F.BOX, 2, 1)),         # FP32, three cells in x and z
 ]
 
 

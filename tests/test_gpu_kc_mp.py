@@ -69,6 +69,8 @@ CASES = [
     ("gauss3_auto", (24, 20, 35), (F.GAUSS, 3, 0), P1),  # FP64, R = 5 (general-tap filter path)
     ("box8_fp32", (19, 34, 37), (F.BOX, 8, 1), P2),      # FP32, R = 4
     ("gauss8_fp32", (28, 36, 40), (F.GAUSS, 8, 1), P1),  # FP32, R = 12
+    ("tiny_box4", (5, 6, 7), (F.BOX, 4, 0), P2),         # 2R + 1 = n along z
+    ("thin_box2", (3, 70, 3), (F.BOX, 2, 1), P1),        # FP32, three cells in x and z
 ]
 
 
