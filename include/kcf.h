@@ -76,6 +76,9 @@ typedef struct {
   float *k_sgs;     /* N   */
   float *nu_t;      /* N   */
   float *omega_t;   /* N   */
+  float *q_crit;    /* N   Q-criterion (|W|^2 - |S|^2)/2 of the gradient (W, S its antisymmetric
+                           and symmetric parts), the vortex indicator of the paper's cavity
+                           and cylinder sections */
 } kcf_outputs;
 
 /* Closure parameters. Pass NULL for the defaults given in brackets. */
@@ -272,13 +275,13 @@ int kcf_sgs_moment3(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filter
  *   k_sgs = |m_sgs_aa| / (2 rho_ref), nu_t_eff = max(nu, C_nu Delta sqrt(k_sgs)),
  *   omega_sgs = (nu_t_eff / theta + dt / 2)^-1     (Delta = the filter width),
  * and the same rates from the exact tau for the statistics. Outputs (device, each may be
- * NULL, but not all of them and stats): m_sgs [6][N] (xx xy xz yy yz zz), k_sgs, nu_t_eff,
- * omega_sgs [N]. The call runs the filter path (kcf_filter_favre, into a context scratch of
+ * NULL, but not all of them and stats): m_sgs and m_ce [6][N] (xx xy xz yy yz zz), k_sgs,
+ * nu_t_eff, omega_sgs [N]. The call runs the filter path (kcf_filter_favre, into a context scratch of
  * 16 N floats for rho_bar, tau and G), then filters rho S_ij in z slabs (two timed kernels
  * per slab); with stats it synchronises.
  * Errors: as kcf_sgs_carrier; KCF_EINVAL for a NULL or out-of-range kp. */
 int kcf_kc_mp(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filter, const float *rho,
-              const float *u, const kcf_kc_params *kp, float *m_sgs, float *k_sgs,
+              const float *u, const kcf_kc_params *kp, float *m_sgs, float *m_ce, float *k_sgs,
               float *nu_t_eff, float *omega_sgs, kcf_kc_stats *stats);
 
 /* E_k, enstrophy and <rho> of the unfiltered input (synchronises). */

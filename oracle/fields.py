@@ -172,6 +172,14 @@ def strain_rotation(G):
     return 0.5 * (G + GT), 0.5 * (G - GT)
 
 
+def q_criterion(G):
+    """Q = (|W|^2 - |S|^2) / 2 with the Frobenius norms of the antisymmetric and symmetric
+    parts of the gradient (the Q-criterion the paper shows for its wake and cavity flows,
+    Secs. "Flow in a lid-driven cavity" and "Flow past a circular cylinder")."""
+    S, W = strain_rotation(G)
+    return 0.5 * (np.einsum("ij...,ij...->...", W, W) - np.einsum("ij...,ij...->...", S, S))
+
+
 def curl6(u, h: float):
     """Vorticity with sixth-order central differences (Sec. "Taylor-Green vortex":
     enstrophy diagnostics use a sixth-order centered stencil). Standard coefficients

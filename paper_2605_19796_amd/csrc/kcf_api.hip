@@ -155,6 +155,7 @@ void set_outputs(WidthArgs& W, const kcf_outputs* o) {
   W.k_sgs = o->k_sgs;
   W.nu_t = o->nu_t;
   W.omega_t = o->omega_t;
+  W.q_crit = o->q_crit;
 }
 
 // Statistics of one width from its 40 FP64 sums.
@@ -505,7 +506,7 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     WidthArgs W;
     fill_width(W, f);
     const bool grad_pass = stats || W.grad || W.tau_gm || W.tau_smag || W.k_sgs || W.nu_t ||
-                           W.omega_t;
+                           W.omega_t || W.q_crit;
     float* fb = W.rho_bar;
     float* fu = W.ut;
     float* ft = W.tau;
@@ -662,13 +663,13 @@ int kcf_sgs_moment3(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, 
 }
 
 int kcf_kc_mp(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, const float* rho,
-              const float* u, const kcf_kc_params* kp, float* m_sgs, float* k_sgs,
+              const float* u, const kcf_kc_params* kp, float* m_sgs, float* m_ce, float* k_sgs,
               float* nu_t_eff, float* omega_sgs, kcf_kc_stats* stats) {
   if (!c) return fail(KCF_EINVAL, "ctx is NULL");
   int rc = check_grid(grid);
   if (rc) return rc;
   if (!filter || !rho || !u || !kp) return fail(KCF_EINVAL, "NULL argument");
-  if (!m_sgs && !k_sgs && !nu_t_eff && !omega_sgs && !stats)
+  if (!m_sgs && !m_ce && !k_sgs && !nu_t_eff && !omega_sgs && !stats)
     return fail(KCF_EINVAL, "nothing requested");
   if (!(kp->nu >= 0) || !(kp->dt >= 0) || !(kp->theta > 0) || !(kp->c_nu >= 0) ||
       (kp->rho_ref_one != 0 && kp->rho_ref_one != 1))
@@ -690,6 +691,7 @@ int kcf_kc_mp(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, const 
   A.u = u;
   A.ext = c->d_kc;
   A.m_sgs = m_sgs;
+  A.m_ce = m_ce;
   A.k_sgs = k_sgs;
   A.nu_t_eff = nu_t_eff;
   A.omega_sgs = omega_sgs;

@@ -247,7 +247,8 @@ __device__ __forceinline__ void write_stats(double* part, const StatAcc& a) {
 
 // Whether the gradient epilogue has anything to produce (uniform over the launch).
 __device__ __forceinline__ bool needs_gradient(const WidthArgs& W) {
-  return W.partials || W.grad || W.tau_gm || W.tau_smag || W.k_sgs || W.nu_t || W.omega_t;
+  return W.partials || W.grad || W.tau_gm || W.tau_smag || W.k_sgs || W.nu_t || W.omega_t ||
+         W.q_crit;
 }
 
 __device__ __forceinline__ void store_point(const WidthArgs& W, int64_t g, int64_t ntot,
@@ -269,6 +270,14 @@ __device__ __forceinline__ void store_point(const WidthArgs& W, int64_t g, int64
   if (W.k_sgs) W.k_sgs[g] = P.ksgs;
   if (W.nu_t) W.nu_t[g] = P.nut;
   if (W.omega_t) W.omega_t[g] = P.omt;
+  if (W.q_crit) {  // (|W|^2 - |S|^2) / 2 = -G_ij G_ji / 2
+    float q = 0.f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) q = fmaf(P.G[i][j], P.G[j][i], q);
+    W.q_crit[g] = -0.5f * q;
+  }
 }
 
 // Tile t of a z-chunk -> tile coordinates. With strip_w > 0 tiles are numbered in vertical

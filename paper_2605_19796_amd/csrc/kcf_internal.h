@@ -27,6 +27,7 @@ struct WidthArgs {          // outputs, closure constants and statistics of one 
   float* k_sgs;
   float* nu_t;
   float* omega_t;
+  float* q_crit;
   float gm_coef;          // C2 of the gradient model
   float smag_coef;        // (C_s Delta)^2
   float cnu_delta;        // C_nu Delta
@@ -135,6 +136,7 @@ struct MonoArgs {
   // KC-MP evaluation
   const float* ext;        // stored filtered fields: rho_bar [N], tau [6N], G [9N]
   float* m_sgs;            // [6][N], or NULL
+  float* m_ce;             // [6][N], or NULL
   float* k_sgs;            // [N], or NULL
   float* nu_t_eff;         // [N], or NULL
   float* omega_sgs;        // [N], or NULL

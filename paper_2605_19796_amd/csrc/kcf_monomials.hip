@@ -353,6 +353,10 @@ struct KcSet {
 #pragma unroll
         for (int c = 0; c < 6; ++c) A.m_sgs[c * N + g] = m[c];
       }
+      if (A.m_ce) {  // -2 rho_bar theta tau_hat S_t
+#pragma unroll
+        for (int c = 0; c < 6; ++c) A.m_ce[c * N + g] = -A.kc_coef * rb * St[c];
+      }
       if (A.k_sgs) A.k_sgs[g] = k;
       if (A.nu_t_eff) A.nu_t_eff[g] = nue;
       if (A.omega_sgs) A.omega_sgs[g] = om;

@@ -33,7 +33,8 @@ class Filter(C.Structure):
 
 class Outputs(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in
-                ("rho_bar", "ut", "tau", "grad", "tau_gm", "tau_smag", "k_sgs", "nu_t", "omega_t")]
+                ("rho_bar", "ut", "tau", "grad", "tau_gm", "tau_smag", "k_sgs", "nu_t", "omega_t",
+                 "q_crit")]
 
 
 class ClosureParams(C.Structure):
@@ -119,7 +120,7 @@ _SIGS = {
                                   C.POINTER(Moment3Stats)]),
     "kcf_kc_mp": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.POINTER(Filter), C.c_void_p,
                             C.c_void_p, C.POINTER(KcParams), C.c_void_p, C.c_void_p, C.c_void_p,
-                            C.c_void_p, C.POINTER(KcStats)]),
+                            C.c_void_p, C.c_void_p, C.POINTER(KcStats)]),
     "kcf_input_stats": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p,
                                   C.POINTER(InputSummary)]),
     "kcf_reduce_check": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -204,7 +205,8 @@ def params(c_s=0.11, c_nu=0.02, theta=1.0, nu_mol=0.0, dt=0.0, gm_form=0, m2_mod
     return ClosureParams(c_s, c_nu, theta, nu_mol, dt, gm_form, m2_mode, ksgs_rho_ref)
 
 
-OUT_SIZES = dict(rho_bar=1, ut=3, tau=6, grad=9, tau_gm=6, tau_smag=6, k_sgs=1, nu_t=1, omega_t=1)
+OUT_SIZES = dict(rho_bar=1, ut=3, tau=6, grad=9, tau_gm=6, tau_smag=6, k_sgs=1, nu_t=1, omega_t=1,
+                 q_crit=1)
 
 
 def alloc_outputs(shape, device, fields=("rho_bar", "ut", "tau", "grad", "tau_gm")):
@@ -318,9 +320,9 @@ class Context:
         return st.as_dict() if stats else None
 
     def kc_mp(self, rho, u, h, filt, nu, dt=0.0, theta=1.0, c_nu=0.035, rho_ref_one=1,
-              m_sgs=None, k_sgs=None, nu_t_eff=None, omega_sgs=None, stats=True):
+              m_sgs=None, m_ce=None, k_sgs=None, nu_t_eff=None, omega_sgs=None, stats=True):
         """A priori KC-MP SGS moment and relaxation-rate field of one filter (kind, n[,
-        precision]); outputs are optional device float32 tensors ((6, nz, ny, nx) for m_sgs,
+        precision]); outputs are optional device float32 tensors ((6, nz, ny, nx) for m_sgs and m_ce,
         (nz, ny, nx) for the rates). Returns the statistics dict or None."""
         nz, ny, nx = rho.shape
         g = Grid(nx, ny, nz, h)
@@ -328,7 +330,7 @@ class Context:
         kp = KcParams(nu, dt, theta, c_nu, rho_ref_one)
         st = KcStats() if stats else None
         check(self._lib.kcf_kc_mp(self.handle, C.byref(g), C.byref(fl), _ptr(rho), _ptr(u),
-                                  C.byref(kp), _ptr(m_sgs), _ptr(k_sgs), _ptr(nu_t_eff),
+                                  C.byref(kp), _ptr(m_sgs), _ptr(m_ce), _ptr(k_sgs), _ptr(nu_t_eff),
                                   _ptr(omega_sgs), C.byref(st) if stats else None))
         return st.as_dict() if stats else None
 

@@ -19,7 +19,7 @@ from paper_2605_19796_amd import kcf, synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
-ALL = ("rho_bar", "ut", "tau", "grad", "tau_gm", "tau_smag", "k_sgs", "nu_t", "omega_t")
+ALL = ("rho_bar", "ut", "tau", "grad", "tau_gm", "tau_smag", "k_sgs", "nu_t", "omega_t", "q_crit")
 PAIRS = F.PAIRS
 
 
@@ -54,7 +54,7 @@ def oracle_as_gpu_layout(o):
     return dict(rho_bar=o["rho_bar"][None], ut=o["ut"], tau=sym(o["tau"]),
                 grad=o["G"].reshape((9,) + o["G"].shape[2:]), tau_gm=sym(o["tau_gm"]),
                 tau_smag=sym(o["tau_smag"]), k_sgs=o["k_sgs"][None], nu_t=o["nu_t"][None],
-                omega_t=o["omega_t"][None])
+                omega_t=o["omega_t"][None], q_crit=F.q_criterion(o["G"])[None])
 
 
 def run_gpu(ctx, rho, u, h, filters, fields=ALL, cp=None):

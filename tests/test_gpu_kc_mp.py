@@ -52,11 +52,12 @@ def seed_of(name):
     return zlib.crc32(name.encode()) & 0xFFFF
 
 
-def run(ctx, rho, u, h, filt, p, stats=True):
+def run(ctx, rho, u, h, filt, p, stats=True, m_ce=None):
     nz, ny, nx = rho.shape
     m = torch.empty((6, nz, ny, nx), dtype=torch.float32, device="cuda")
     k, nue, om = (torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda") for _ in range(3))
-    st = ctx.kc_mp(rho, u, h, filt, m_sgs=m, k_sgs=k, nu_t_eff=nue, omega_sgs=om, stats=stats, **p)
+    st = ctx.kc_mp(rho, u, h, filt, m_sgs=m, m_ce=m_ce, k_sgs=k, nu_t_eff=nue, omega_sgs=om,
+                   stats=stats, **p)
     torch.cuda.synchronize()
     return m, k, nue, om, st
 
@@ -79,12 +80,15 @@ def test_full_field_parity(ctx, name, shape, filt, p):
     say(f"[gpu] kc-mp {name} {shape} filter {filt}")
     rho_h, u_h = synth.random_fields(shape, seed=seed_of(name), rho_amp=0.2)
     h = 2 * math.pi / shape[2]
-    m, k, nue, om, st = run(ctx, dev(rho_h), dev(u_h), h, filt, p)
+    mce = torch.empty((6,) + shape, dtype=torch.float32, device="cuda")
+    m, k, nue, om, st = run(ctx, dev(rho_h), dev(u_h), h, filt, p, m_ce=mce)
     o = KC.kc_mp(rho_h, u_h, filt[0], filt[1], h, p["nu"], p["dt"], p["theta"], p["c_nu"],
                  bool(p["rho_ref_one"]))
     g = m.cpu().numpy()
+    gce = mce.cpu().numpy()
     for c, (i, j) in enumerate(F.PAIRS):
         assert rel(g[c], o["m_sgs"][i, j]) <= TOL, (c, rel(g[c], o["m_sgs"][i, j]))
+        assert rel(gce[c], o["m_ce"][i, j]) <= TOL, (c, rel(gce[c], o["m_ce"][i, j]))
     for got, key in ((k, "k_sgs"), (nue, "nu_t_eff"), (om, "omega_sgs")):
         assert rel(got.cpu().numpy(), o[key]) <= TOL, (key, rel(got.cpu().numpy(), o[key]))
     n = int(np.prod(shape))

@@ -324,3 +324,18 @@ def test_sampled_points_match_full_field():
             assert np.max(np.abs(sp["G"][idx] - full["G"][:, :, k, j, i])) < 1e-12
             assert np.max(np.abs(sp["tau_gm"][idx] - full["tau_gm"][:, :, k, j, i])) < 1e-14
             assert abs(sp["k_sgs"][idx] - full["k_sgs"][k, j, i]) < 1e-14
+
+
+def test_q_criterion_cases():
+    """Solid-body rotation has Q = |W|^2 / 2 = omega^2 / 2 > 0, pure strain Q = -|S|^2 / 2,
+    and in general Q = -G_ij G_ji / 2."""
+    om = 0.7
+    G = np.zeros((3, 3, 1))
+    G[0, 1, 0], G[1, 0, 0] = -om, om  # u = omega x (0, 0, 1) x r
+    assert abs(F.q_criterion(G)[0] - om * om) < 1e-15  # |W|_F^2 = 2 om^2
+    Gs = np.zeros((3, 3, 1))
+    Gs[0, 0, 0], Gs[1, 1, 0], Gs[2, 2, 0] = 1.0, -0.4, -0.6
+    assert abs(F.q_criterion(Gs)[0] + 0.5 * (1.0 + 0.16 + 0.36)) < 1e-15
+    rng = np.random.default_rng(3)
+    Gr = rng.standard_normal((3, 3, 5))
+    assert np.allclose(F.q_criterion(Gr), -0.5 * np.einsum("ij...,ji...->...", Gr, Gr), atol=1e-14)
