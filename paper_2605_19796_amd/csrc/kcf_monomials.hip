@@ -609,9 +609,10 @@ struct XyLds {
   static constexpr int HXP = HX | 1;  // odd row stride
   static constexpr int NRAW = HX * HY;
   static constexpr int QS = HY * HXP;
-  // quantities per LDS round: nine while they fit in 68 KiB (two workgroups per CU), else
-  // three
-  static constexpr int G = 9 * QS * (int)sizeof(T) <= 69632 ? 9 : 3;
+  // quantities per LDS round: as many as fit in 40 KiB, so that three or four workgroups
+  // share a CU (measured faster than fewer, larger rounds)
+  static constexpr int G0 = 40960 / (QS * (int)sizeof(T));
+  static constexpr int G = G0 < 1 ? 1 : (G0 > NQ ? NQ : G0);
   static constexpr int doubles = (G * QS * (int)sizeof(T) + 7) / 8;
 };
 
