@@ -1,5 +1,5 @@
-// Filtered monomials rho u_x^a u_y^b u_z^c (and rho theta) and the SGS quantities built from
-// them, as two streaming kernels per z slab shared by two quantity sets:
+// Filtered monomials rho u_x^a u_y^b u_z^c (and rho theta, rho S_ij) and the SGS quantities
+// built from them, as two streaming kernels per z slab shared by three quantity sets:
 //
 //   carrier  the a priori SGS carrier of the D3Q27 lattice, f_sgs,i = bar(f0_i(rho, u)) -
 //            f0_i(rho_bar, ut) (eqs. f0bar and fsgs_def) with the product equilibrium of
@@ -24,13 +24,14 @@
 // Hermite order of a term (eq. f_sgs_hermite on the tensor-product lattice).
 //
 //   k_*_z   one thread per (x, y) column and ZT planes: the set's products of the input,
-//           one group of up to nine at a time, filtered along z over a register window of
-//           the input planes and written to the slab buffer [quantities][planes][ny][nx];
+//           one group of up to nine at a time (k_kc_z: the six rho S_ij, with the x and y
+//           neighbours of each point), filtered along z over a register window of the input
+//           planes and written to the slab buffer [quantities][planes][ny][nx];
 //   k_*_xy  one workgroup per (tile of 256 points, run of eight planes), XCD-banded: per plane,
 //           the quantities of the tile and its halo staged in LDS G at a time, filtered along
 //           x and y in place, each thread keeping its point's filtered values; then the set's
 //           epilogue (stores and statistics: a point's values in FP32, their sums over points
-//           in FP64, one record per workgroup).
+//           in FP64; one record per workgroup, or per wave for the 40 folded KC-MP sums).
 // T is the type of the products, of both filter passes and of the slab buffer (double for
 // narrow widths, as in the Favre path); the differences against the Favre fields are formed
 // in T, what follows them in FP32.
