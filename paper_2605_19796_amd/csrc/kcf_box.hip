@@ -9,10 +9,12 @@
 //     read a second time, from cache) are prefetched one step ahead and turned into the
 //     differences d = P(za) - P(za - 2R) of the ten products P = rho, rho u_i, rho u_i u_j;
 //   * x pass and y pass, in place in one LDS buffer: each task slides a trapezoid window
-//     over one row (column) of one quantity in registers, about four operations per output;
+//     over one row (column) of one quantity in registers, three operations per output (the
+//     window is formed as the sum of two boxcars, unscaled: each pass multiplies by 2n);
 //   * z: since the x-y filter is linear, the filtered d is the change of the 2R-plane boxcar
 //     sum B of the filtered products; B is kept per column thread in FP64, and the trapezoid
-//     of plane za - R is the mean of two consecutive boxcars, (B_{k-1} + B_k) / (2n);
+//     of plane za - R is the mean of two consecutive boxcars, (B_{k-1} + B_k) / (2n), and
+//     the factors of the x and y passes are divided out with it;
 //   * epilogue: Favre velocity and tau from the FP64 window sums; the velocity of three
 //     planes goes to LDS for the gradient, which is evaluated one plane behind together
 //     with the closures and the FP64 statistics.
@@ -52,6 +54,14 @@ using TallTile = BoxCfg<28, 512, 2, 8>;
 template <int R>
 using TileFor = typename std::conditional<(R <= 4), ShortTile, TallTile>::type;
 
+// Waves per SIMD of a (radius, precision) pair: the tile's, except double products with
+// R >= 3, whose LDS buffer leaves room for two workgroups per CU and whose x-y windows need
+// more than the 168 registers of three waves.
+template <int R, typename T>
+constexpr int box_waves() {
+  return sizeof(T) == 8 && R >= 3 ? 2 : TileFor<R>::WAVES;
+}
+
 // One buffer of 10 planes of HY rows with an odd row stride (conflict-free row-per-lane
 // access): products, then x-filtered rows (first kBX entries), then y-filtered rows.
 template <int R, typename T, class C = TileFor<R>>
@@ -67,23 +77,26 @@ struct BoxLds {
   static constexpr int bytes = prod + su;
   static constexpr int doubles = (bytes + 7) / 8;
   // resident workgroups per CU: the smaller of the register and the LDS limit
-  static constexpr int by_waves = C::WAVES * 4 / (C::BT / 64);
+  static constexpr int by_waves = box_waves<R, T>() * 4 / (C::BT / 64);
   static constexpr int by_lds = kLdsPerCU / bytes;
   static constexpr int blocks_per_cu = by_waves < by_lds ? by_waves : by_lds;
 };
 
-// Trapezoid window over v[o .. o + 2R]: (1/n)(sum of the interior + half the two ends).
-// J holds v[o+1] + ... + v[o+2R] on entry and is advanced to the next output.
-template <int R, typename T>
-__device__ __forceinline__ T trap_slide(const T* v, int o, T& J, T inv_n) {
-  const T out = inv_n * (J + (T)0.5 * (v[o] - v[o + 2 * R]));
-  J += v[o + 2 * R + 1] - v[o + 1];
-  return out;
-}
-
-template <int R, typename T>
-__device__ __forceinline__ T trap_last(const T* v, int o, T J, T inv_n) {
-  return inv_n * (J + (T)0.5 * (v[o] - v[o + 2 * R]));
+// Trapezoid windows over v[o .. o + 2R], o = 0 .. NO - 1, each scaled by 2n = 4R: with
+// S_o = v[o] + ... + v[o + 2R - 1] the 2R-point boxcar, 2n times the trapezoid (ends 1/(2n),
+// interior 1/n) is S_o + S_{o+1}. Three operations per output; the factor 2n of each pass
+// is divided out once, in double, after the z sum.
+template <int R, int NO, typename T, class St>
+__device__ __forceinline__ void trap_row(const T* v, St&& store) {
+  T S = v[0];
+#pragma unroll
+  for (int i = 1; i < 2 * R; ++i) S += v[i];
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const T Sn = S + (v[o + 2 * R] - v[o]);
+    store(o, S + Sn);
+    S = Sn;
+  }
 }
 
 template <typename T>
@@ -118,8 +131,8 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   constexpr int NI = L::NI;
   float* su = reinterpret_cast<float*>(smem + L::prod);  // 3 planes x 3 x kBN
   float* lagb = su + 9 * kBN;                             // 2 planes x 7 x NI
-  const T inv_n = (T)1 / (T)(2 * R);
-  const double inv_2n = 1.0 / (4.0 * R);
+  // the mean of two z boxcars, and the factor 4R of each of the x and y passes
+  const double inv_2n = 1.0 / ((4.0 * R) * (4.0 * R) * (4.0 * R));
 
   const int tid = threadIdx.x;
   const int tile = item % A.ntiles;
@@ -175,7 +188,8 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   double B[10];  // boxcar sums of the 2R planes za - 2R + 1 .. za
 #pragma unroll
   for (int q = 0; q < 10; ++q) B[q] = 0.0;
-  StatAcc acc;
+  // tall tiles run at two waves per SIMD and keep all 40 sums per lane
+  typename std::conditional<(kBT >= 512), StatLane, StatAcc>::type acc;
   stat_zero(acc);
   const bool need_grad = needs_gradient(W);
 
@@ -209,12 +223,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
       T vr[HX];
 #pragma unroll
       for (int i = 0; i < HX; ++i) vr[i] = v[i];
-      T J = 0;
-#pragma unroll
-      for (int i = 1; i <= 2 * R; ++i) J += vr[i];
-#pragma unroll
-      for (int o = 0; o < kBX - 1; ++o) v[o] = trap_slide<R, T>(vr, o, J, inv_n);
-      v[kBX - 1] = trap_last<R, T>(vr, kBX - 1, J, inv_n);
+      trap_row<R, kBX>(vr, [&](int o, T x) { v[o] = x; });
     }
     __syncthreads();
     // ---- y pass, in place: one (quantity, column, half of the rows) per task; all reads
@@ -240,12 +249,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         if (t < NYT) {
           const int x = t % kBX, part = (t / kBX) % kYP, q = t / (kYP * kBX);
           T* dst = buf + q * QS + part * kBYP * HXP + x;
-          T J = 0;
-#pragma unroll
-          for (int i = 1; i <= 2 * R; ++i) J += vr[j][i];
-#pragma unroll
-          for (int o = 0; o < kBYP - 1; ++o) dst[o * HXP] = trap_slide<R, T>(vr[j], o, J, inv_n);
-          dst[(kBYP - 1) * HXP] = trap_last<R, T>(vr[j], kBYP - 1, J, inv_n);
+          trap_row<R, kBYP>(vr[j], [&](int o, T x) { dst[o * HXP] = x; });
         }
       }
     }
@@ -339,7 +343,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
 
 template <int R, typename T>
 __global__ void __launch_bounds__(TileFor<R>::BT)
-    __attribute__((amdgpu_waves_per_eu(TileFor<R>::WAVES, TileFor<R>::WAVES)))
+    __attribute__((amdgpu_waves_per_eu(box_waves<R, T>(), box_waves<R, T>())))
     k_box1(FilterArgs A) {
   __shared__ double smem[BoxLds<R, T>::doubles];
   int item;

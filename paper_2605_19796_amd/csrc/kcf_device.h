@@ -245,6 +245,30 @@ __device__ __forceinline__ void write_stats(double* part, const StatAcc& a) {
   }
 }
 
+// Per-lane sums of all 40 slots, with no lane swaps per point: for kernels whose register
+// budget has room for them (80 registers). The wave reduction at the end applies the same
+// fixed-order fold to the lane sums.
+struct StatLane {
+  double s[kNStat];
+};
+
+__device__ __forceinline__ void stat_zero(StatLane& a) {
+#pragma unroll
+  for (int k = 0; k < kNStat; ++k) a.s[k] = 0.0;
+}
+
+__device__ __forceinline__ void stat_add(const StatIn& I, StatLane& a) {
+#pragma unroll
+  for (int k = 0; k < kNStat; ++k) a.s[k] += stat_val(I, k);
+}
+
+__device__ __forceinline__ void write_stats(double* part, const StatLane& a) {
+  StatAcc f;
+  stat_zero(f);
+  stat_fold([&](int s) { return a.s[s]; }, f);
+  write_stats(part, f);
+}
+
 // Whether the gradient epilogue has anything to produce (uniform over the launch).
 __device__ __forceinline__ bool needs_gradient(const WidthArgs& W) {
   return W.partials || W.grad || W.tau_gm || W.tau_smag || W.k_sgs || W.nu_t || W.omega_t ||
