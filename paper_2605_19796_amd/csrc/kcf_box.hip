@@ -64,6 +64,10 @@ constexpr int box_waves() {
 
 // One buffer of 10 planes of HY rows with an odd row stride (conflict-free row-per-lane
 // access): products, then x-filtered rows (first kBX entries), then y-filtered rows.
+// Tall tiles have the LDS to spare for a separate y output and deeper rings, which removes
+// two of the five barriers of a step: the y pass no longer works in place, and the gradient
+// epilogue runs two planes behind the window instead of one, on planes written in earlier
+// steps.
 template <int R, typename T, class C = TileFor<R>>
 struct BoxLds {
   static constexpr int HX = kBX + 2 * R;
@@ -72,9 +76,14 @@ struct BoxLds {
   static constexpr int NRAW = HX * HY;
   static constexpr int prod = (10 * HY * HXP * (int)sizeof(T) + 15) / 16 * 16;
   static constexpr int NI = kBOX * C::BOY;  // interior (output) columns
-  // ut of three planes, then rho_bar and tau of the interior columns of two planes
-  static constexpr int su = (9 * C::BN + 14 * NI) * 4;
-  static constexpr int bytes = prod + su;
+  static constexpr bool split = C::BT >= 512;
+  static constexpr int D = split ? 2 : 1;       // planes between the window and the gradient
+  static constexpr int NSU = D + 2;             // planes of ut kept for the gradient
+  static constexpr int NLG = D + 1;             // planes of rho_bar and tau kept for it
+  static constexpr int yout = split ? (10 * C::BY * kBX * (int)sizeof(T) + 15) / 16 * 16 : 0;
+  // ut of NSU planes, then rho_bar and tau of the interior columns of NLG planes
+  static constexpr int su = (NSU * 3 * C::BN + NLG * 7 * NI) * 4;
+  static constexpr int bytes = prod + yout + su;
   static constexpr int doubles = (bytes + 7) / 8;
   // resident workgroups per CU: the smaller of the register and the LDS limit
   static constexpr int by_waves = box_waves<R, T>() * 4 / (C::BT / 64);
@@ -129,8 +138,11 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   constexpr int QS = HY * HXP;  // stride of one quantity in the buffer
   T* buf = reinterpret_cast<T*>(smem);
   constexpr int NI = L::NI;
-  float* su = reinterpret_cast<float*>(smem + L::prod);  // 3 planes x 3 x kBN
-  float* lagb = su + 9 * kBN;                             // 2 planes x 7 x NI
+  constexpr bool kSplit = L::split;
+  constexpr int D = L::D, NSU = L::NSU, NLG = L::NLG;
+  T* yb = reinterpret_cast<T*>(smem + L::prod);                     // split: 10 x BY x kBX
+  float* su = reinterpret_cast<float*>(smem + L::prod + L::yout);  // NSU planes x 3 x kBN
+  float* lagb = su + NSU * 3 * kBN;                                 // NLG planes x 7 x NI
   // the mean of two z boxcars, and the factor 4R of each of the x and y passes
   const double inv_2n = 1.0 / ((4.0 * R) * (4.0 * R) * (4.0 * R));
 
@@ -142,36 +154,50 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   const int x0 = tx * kBOX - 1, y0 = ty * kBOY - 1;  // global coordinates of column (0, 0)
   const int z0 = zc * A.zlen;
   const int z1 = min(z0 + A.zlen, A.nz);
-  const int nsteps = (z1 - z0) + 2 * R + 2;
+  const int nfilt = (z1 - z0) + 2 * R + 2;  // steps that bring in a plane
+  const int nsteps = nfilt + D - 1;         // and those that only finish the gradient
   const int za0 = z0 - 1 - R;
   const int64_t plane = (int64_t)A.nx * A.ny;
   const int64_t ntot = A.ntot;
 
-  int pfoff[NPF], ldoff[NPF];
+  // raw points of this thread: byte offsets within a plane (below 2^32: a plane holds at
+  // most 2^30 points) and LDS offsets; only the last round can hold threads without a point
+  uint32_t pfoff[NPF];
+  int ldoff[NPF];
+  bool has[NPF];
 #pragma unroll
   for (int i = 0; i < NPF; ++i) {
     const int p = tid + i * kBT;
-    if (p < NRAW) {
+    has[i] = (i + 1) * kBT <= NRAW || p < NRAW;
+    if (has[i]) {
       const int hx = p % HX, hy = p / HX;
-      pfoff[i] = wrapi(y0 - R + hy, A.ny) * A.nx + wrapi(x0 - R + hx, A.nx);
+      pfoff[i] = (uint32_t)(wrapi(y0 - R + hy, A.ny) * A.nx + wrapi(x0 - R + hx, A.nx)) * 4u;
       ldoff[i] = hy * HXP + hx;
     } else {
-      pfoff[i] = -1;
+      pfoff[i] = 0;
       ldoff[i] = 0;
     }
   }
-  // inputs of the arriving plane (pn) and of the plane leaving the window (po)
+  // inputs of the arriving plane (pn) and of the plane leaving the window (po); the plane's
+  // base addresses are uniform, so each load is a scalar base plus this thread's offset
   float pn[NPF][4], po[NPF][4];
   auto load = [&](float (&pf)[NPF][4], int za) {
     const int64_t zoff = (int64_t)wrapi(za, A.nz) * plane;
+    const char* b0 = reinterpret_cast<const char*>(A.rho + zoff);
+    const char* b1 = reinterpret_cast<const char*>(A.u + zoff);
+    const char* b2 = reinterpret_cast<const char*>(A.u + ntot + zoff);
+    const char* b3 = reinterpret_cast<const char*>(A.u + 2 * ntot + zoff);
 #pragma unroll
     for (int i = 0; i < NPF; ++i) {
-      if (pfoff[i] >= 0) {
-        const int64_t g = zoff + pfoff[i];
-        pf[i][0] = A.rho[g];
-        pf[i][1] = A.u[g];
-        pf[i][2] = A.u[g + ntot];
-        pf[i][3] = A.u[g + 2 * ntot];
+      if (has[i]) {
+        // opaque here, so that the 32-bit offset is not widened once outside the loop
+        // (which would cost a 64-bit address add per load instead of the scalar-base form)
+        uint32_t o = pfoff[i];
+        __asm__ volatile("" : "+v"(o));
+        pf[i][0] = *reinterpret_cast<const float*>(b0 + o);
+        pf[i][1] = *reinterpret_cast<const float*>(b1 + o);
+        pf[i][2] = *reinterpret_cast<const float*>(b2 + o);
+        pf[i][3] = *reinterpret_cast<const float*>(b3 + o);
       }
     }
   };
@@ -184,6 +210,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   const bool interior = col_thread && cx >= 1 && cx <= kBOX && cy >= 1 && cy <= kBOY &&
                         gx < A.nx && gy < A.ny;
   const int ycol = cy * HXP + cx;  // this column's entry in a y-filtered plane
+  const uint32_t cofs = interior ? (uint32_t)(gy * A.nx + gx) * 4u : 0u;  // bytes in a plane
 
   double B[10];  // boxcar sums of the 2R planes za - 2R + 1 .. za
 #pragma unroll
@@ -195,125 +222,138 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
 
   for (int k = 0; k < nsteps; ++k) {
     const int za = za0 + k;
-    const bool leaving = k >= 2 * R;  // uniform: plane za - 2R is inside the window
-    // ---- staging: product differences of plane za
+    const int zo = za - R;
+    const int us = (k - 2 * R + NSU) % NSU;  // ut slot of plane zo
+    if (k < nfilt) {  // uniform
+      const bool leaving = k >= 2 * R;  // uniform: plane za - 2R is inside the window
+      // ---- staging: product differences of plane za
 #pragma unroll
-    for (int i = 0; i < NPF; ++i) {
-      if (pfoff[i] >= 0) {
-        T d[10];
-        products<T>(pn[i], d);
-        if (leaving) {
-          T o[10];
-          products<T>(po[i], o);
+      for (int i = 0; i < NPF; ++i) {
+        if (has[i]) {
+          T d[10];
+          products<T>(pn[i], d);
+          if (leaving) {
+            T o[10];
+            products<T>(po[i], o);
 #pragma unroll
-          for (int q = 0; q < 10; ++q) d[q] -= o[q];
-        }
+            for (int q = 0; q < 10; ++q) d[q] -= o[q];
+          }
 #pragma unroll
-        for (int q = 0; q < 10; ++q) buf[q * QS + ldoff[i]] = d[q];
-      }
-    }
-    __syncthreads();
-    if (k + 1 < nsteps) {
-      load(pn, za + 1);
-      if (k + 1 >= 2 * R) load(po, za + 1 - 2 * R);
-    }
-    // ---- x pass, in place: one (quantity, row) per task
-    for (int t = tid; t < 10 * HY; t += kBT) {
-      T* v = buf + t * HXP;
-      T vr[HX];
-#pragma unroll
-      for (int i = 0; i < HX; ++i) vr[i] = v[i];
-      trap_row<R, kBX>(vr, [&](int o, T x) { v[o] = x; });
-    }
-    __syncthreads();
-    // ---- y pass, in place: one (quantity, column, half of the rows) per task; all reads
-    // are done before the barrier, all writes after it
-    {
-      constexpr int NYT = 10 * kYP * kBX;
-      constexpr int NYI = (NYT + kBT - 1) / kBT;
-      T vr[NYI][kBYP + 2 * R];
-#pragma unroll
-      for (int j = 0; j < NYI; ++j) {
-        const int t = tid + j * kBT;
-        if (t < NYT) {
-          const int x = t % kBX, part = (t / kBX) % kYP, q = t / (kYP * kBX);
-          const T* src = buf + q * QS + part * kBYP * HXP + x;
-#pragma unroll
-          for (int i = 0; i < kBYP + 2 * R; ++i) vr[j][i] = src[i * HXP];
+          for (int q = 0; q < 10; ++q) buf[q * QS + ldoff[i]] = d[q];
         }
       }
       __syncthreads();
+      if (k + 1 < nfilt) {
+        load(pn, za + 1);
+        if (k + 1 >= 2 * R) load(po, za + 1 - 2 * R);
+      }
+      // ---- x pass, in place: one (quantity, row) per task
+      for (int t = tid; t < 10 * HY; t += kBT) {
+        T* v = buf + t * HXP;
+        T vr[HX];
 #pragma unroll
-      for (int j = 0; j < NYI; ++j) {
-        const int t = tid + j * kBT;
-        if (t < NYT) {
-          const int x = t % kBX, part = (t / kBX) % kYP, q = t / (kYP * kBX);
-          T* dst = buf + q * QS + part * kBYP * HXP + x;
-          trap_row<R, kBYP>(vr[j], [&](int o, T x) { dst[o * HXP] = x; });
+        for (int i = 0; i < HX; ++i) vr[i] = v[i];
+        trap_row<R, kBX>(vr, [&](int o, T x) { v[o] = x; });
+      }
+      __syncthreads();
+      // ---- y pass: one (quantity, column, half of the rows) per task. In place (short tiles):
+      // all reads are done before the barrier, all writes after it; tall tiles write to yb.
+      {
+        constexpr int NYT = 10 * kYP * kBX;
+        constexpr int NYI = (NYT + kBT - 1) / kBT;
+        T vr[NYI][kBYP + 2 * R];
+#pragma unroll
+        for (int j = 0; j < NYI; ++j) {
+          const int t = tid + j * kBT;
+          if (t < NYT) {
+            const int x = t % kBX, part = (t / kBX) % kYP, q = t / (kYP * kBX);
+            const T* src = buf + q * QS + part * kBYP * HXP + x;
+#pragma unroll
+            for (int i = 0; i < kBYP + 2 * R; ++i) vr[j][i] = src[i * HXP];
+          }
+        }
+        if (!kSplit) __syncthreads();
+#pragma unroll
+        for (int j = 0; j < NYI; ++j) {
+          const int t = tid + j * kBT;
+          if (t < NYT) {
+            const int x = t % kBX, part = (t / kBX) % kYP, q = t / (kYP * kBX);
+            if (kSplit) {
+              T* dst = yb + (q * C::BY + part * kBYP) * kBX + x;
+              trap_row<R, kBYP>(vr[j], [&](int o, T x) { dst[o * kBX] = x; });
+            } else {
+              T* dst = buf + q * QS + part * kBYP * HXP + x;
+              trap_row<R, kBYP>(vr[j], [&](int o, T x) { dst[o * HXP] = x; });
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // ---- z: advance the boxcars; the trapezoid of plane zo = za - R is their mean
+      const bool full = k >= 2 * R;
+      double qb[10];
+#pragma unroll
+      for (int q = 0; q < 10; ++q) {
+        const double prev = B[q];
+        B[q] = prev + (double)(kSplit ? yb[q * kBN + col] : buf[q * QS + ycol]);
+        qb[q] = (prev + B[q]) * inv_2n;
+      }
+      if (full) {  // uniform
+        const double rinv = 1.0 / qb[0];
+        const double uT[3] = {qb[1] * rinv, qb[2] * rinv, qb[3] * rinv};
+        const float cur_rb = (float)qb[0];
+        float cur_tau[6];
+        // tau_ij = bar(rho u_i u_j) - bar(rho u_i) ut_j
+        cur_tau[0] = (float)fma(-qb[1], uT[0], qb[4]);
+        cur_tau[1] = (float)fma(-qb[1], uT[1], qb[5]);
+        cur_tau[2] = (float)fma(-qb[1], uT[2], qb[6]);
+        cur_tau[3] = (float)fma(-qb[2], uT[1], qb[7]);
+        cur_tau[4] = (float)fma(-qb[2], uT[2], qb[8]);
+        cur_tau[5] = (float)fma(-qb[3], uT[2], qb[9]);
+        if (col_thread) {
+#pragma unroll
+          for (int i = 0; i < 3; ++i) su[(us * 3 + i) * kBN + col] = (float)uT[i];
+        }
+        if (interior) {  // for the gradient epilogue D steps later
+          float* lg = lagb + (k % NLG) * 7 * NI + (cy - 1) * kBOX + (cx - 1);
+          lg[0] = cur_rb;
+#pragma unroll
+          for (int s = 0; s < 6; ++s) lg[(1 + s) * NI] = cur_tau[s];
+        }
+        if (interior && zo >= z0 && zo < z1) {
+          const int64_t zb = (int64_t)zo * plane;
+          uint32_t o = cofs;
+          __asm__ volatile("" : "+v"(o));  // keeps the scalar-base store form (see load)
+          if (W.rho_bar) *plane_addr(W.rho_bar, 0, ntot, zb, o) = cur_rb;
+          if (W.ut) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) *plane_addr(W.ut, i, ntot, zb, o) = (float)uT[i];
+          }
+          if (W.tau) {
+#pragma unroll
+            for (int s = 0; s < 6; ++s) *plane_addr(W.tau, s, ntot, zb, o) = cur_tau[s];
+          }
         }
       }
     }
-    __syncthreads();
-    // ---- z: advance the boxcars; the trapezoid of plane zo = za - R is their mean
-    const bool full = k >= 2 * R;
-    double qb[10];
-#pragma unroll
-    for (int q = 0; q < 10; ++q) {
-      const double prev = B[q];
-      B[q] = prev + (double)buf[q * QS + ycol];
-      qb[q] = (prev + B[q]) * inv_2n;
-    }
-    const int zo = za - R;
-    const int us = (k - 2 * R + 3) % 3;
-    if (full) {  // uniform
-      const double rinv = 1.0 / qb[0];
-      const double uT[3] = {qb[1] * rinv, qb[2] * rinv, qb[3] * rinv};
-      const float cur_rb = (float)qb[0];
-      float cur_tau[6];
-      // tau_ij = bar(rho u_i u_j) - bar(rho u_i) ut_j
-      cur_tau[0] = (float)fma(-qb[1], uT[0], qb[4]);
-      cur_tau[1] = (float)fma(-qb[1], uT[1], qb[5]);
-      cur_tau[2] = (float)fma(-qb[1], uT[2], qb[6]);
-      cur_tau[3] = (float)fma(-qb[2], uT[1], qb[7]);
-      cur_tau[4] = (float)fma(-qb[2], uT[2], qb[8]);
-      cur_tau[5] = (float)fma(-qb[3], uT[2], qb[9]);
-      if (col_thread) {
-#pragma unroll
-        for (int i = 0; i < 3; ++i) su[(us * 3 + i) * kBN + col] = (float)uT[i];
-      }
-      if (interior) {  // for the gradient epilogue of the next step
-        float* lg = lagb + (k & 1) * 7 * NI + (cy - 1) * kBOX + (cx - 1);
-        lg[0] = cur_rb;
-#pragma unroll
-        for (int s = 0; s < 6; ++s) lg[(1 + s) * NI] = cur_tau[s];
-      }
-      if (interior && zo >= z0 && zo < z1) {
-        const int64_t g = (int64_t)zo * plane + (int64_t)gy * A.nx + gx;
-        if (W.rho_bar) W.rho_bar[g] = cur_rb;
-        if (W.ut) {
-#pragma unroll
-          for (int i = 0; i < 3; ++i) W.ut[i * ntot + g] = (float)uT[i];
-        }
-        if (W.tau) {
-#pragma unroll
-          for (int s = 0; s < 6; ++s) W.tau[s * ntot + g] = cur_tau[s];
-        }
-      }
-    }
-    // every step: the reads of the y-filtered plane are done before the next staging
-    // overwrites it, and the velocity of plane zo is in LDS before the gradient reads it
-    __syncthreads();
-    const int zg = zo - 1;
+    // Short tiles, every step: the reads of the y-filtered plane are done before the next
+    // staging overwrites it, and the velocity of plane zo is in LDS before the gradient
+    // reads it. Tall tiles read only planes of earlier steps here, behind the three barriers
+    // of this step, or behind this one in a step that brings in no plane.
+    if (!kSplit || k >= nfilt) __syncthreads();
+    const int zg = zo - D;
     // ---- epilogue B: gradient, closures, statistics of plane zg, one interior column per
     // thread (the waves past the NI interior columns have nothing to do)
-    if (need_grad && k >= 2 * R + 1 && zg >= z0 && zg < z1 && (tid & ~63) < NI) {  // uniform
-      const int sg = (us + 2) % 3, sm = (us + 1) % 3, sp = us;
+    if (need_grad && k >= 2 * R + D && zg >= z0 && zg < z1 && (tid & ~63) < NI) {  // uniform
+      // ut slots of planes zg - 1, zg, zg + 1
+      const int sm = (us - D - 1 + 2 * NSU) % NSU, sg = (us - D + NSU) % NSU;
+      const int sp = (us - D + 1 + NSU) % NSU;
       const int t = tid < NI ? tid : 0;
       const int ex = 1 + t % kBOX, ey = 1 + t / kBOX;
       const int ecol = ey * kBX + ex;
       const int egx = x0 + ex, egy = y0 + ey;
       const bool valid = tid < NI && egx < A.nx && egy < A.ny;
-      const float* lg = lagb + ((k - 1) & 1) * 7 * NI + t;
+      const float* lg = lagb + ((k - D) % NLG) * 7 * NI + t;
       const float rb = lg[0];
       float tau[6];
 #pragma unroll
@@ -330,7 +370,12 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         u[i] = ui[ecol];
       }
       point_closures(W, rb, tau, P);
-      if (valid) store_point(W, (int64_t)zg * plane + (int64_t)egy * A.nx + egx, ntot, P);
+      if (valid) {
+        const int64_t zb = (int64_t)zg * plane;
+        uint32_t o = (uint32_t)(egy * A.nx + egx) * 4u;
+        __asm__ volatile("" : "+v"(o));
+        store_point_at(W, P, [&](float* b, int c) { return plane_addr(b, c, ntot, zb, o); });
+      }
       if (W.partials) {  // uniform
         StatIn I;
         stat_inputs(rb, u, tau, P, valid, I);

@@ -275,33 +275,51 @@ __device__ __forceinline__ bool needs_gradient(const WidthArgs& W) {
          W.q_crit;
 }
 
-__device__ __forceinline__ void store_point(const WidthArgs& W, int64_t g, int64_t ntot,
-                                            const PointOut& P) {
+// Stores of one point's requested outputs; at(base, c) gives the address of component c of
+// the point in the field that starts at base.
+template <class At>
+__device__ __forceinline__ void store_point_at(const WidthArgs& W, const PointOut& P, At&& at) {
   if (W.grad) {
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) W.grad[(i * 3 + j) * ntot + g] = P.G[i][j];
+      for (int j = 0; j < 3; ++j) *at(W.grad, i * 3 + j) = P.G[i][j];
   }
   if (W.tau_gm) {
 #pragma unroll
-    for (int s = 0; s < 6; ++s) W.tau_gm[s * ntot + g] = P.tgm[s];
+    for (int s = 0; s < 6; ++s) *at(W.tau_gm, s) = P.tgm[s];
   }
   if (W.tau_smag) {
 #pragma unroll
-    for (int s = 0; s < 6; ++s) W.tau_smag[s * ntot + g] = P.tsm[s];
+    for (int s = 0; s < 6; ++s) *at(W.tau_smag, s) = P.tsm[s];
   }
-  if (W.k_sgs) W.k_sgs[g] = P.ksgs;
-  if (W.nu_t) W.nu_t[g] = P.nut;
-  if (W.omega_t) W.omega_t[g] = P.omt;
+  if (W.k_sgs) *at(W.k_sgs, 0) = P.ksgs;
+  if (W.nu_t) *at(W.nu_t, 0) = P.nut;
+  if (W.omega_t) *at(W.omega_t, 0) = P.omt;
   if (W.q_crit) {  // (|W|^2 - |S|^2) / 2 = -G_ij G_ji / 2
     float q = 0.f;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) q = fmaf(P.G[i][j], P.G[j][i], q);
-    W.q_crit[g] = -0.5f * q;
+    *at(W.q_crit, 0) = -0.5f * q;
   }
+}
+
+__device__ __forceinline__ void store_point(const WidthArgs& W, int64_t g, int64_t ntot,
+                                            const PointOut& P) {
+  store_point_at(W, P, [&](float* base, int c) { return base + c * ntot + g; });
+}
+
+// Address of component c of a point in the field at base: plane offset zb (elements, uniform)
+// plus the point's byte offset o within the plane (below 2^32), the form that compiles to a
+// scalar base and a 32-bit vector offset. The component's offset is made opaque so that the
+// compiler does not share one 64-bit vector address between components.
+__device__ __forceinline__ float* plane_addr(float* base, int c, int64_t ntot, int64_t zb,
+                                             uint32_t o) {
+  int64_t off = (c * ntot + zb) * (int64_t)sizeof(float);
+  __asm__ volatile("" : "+s"(off));
+  return reinterpret_cast<float*>(reinterpret_cast<char*>(base) + off + o);
 }
 
 // Tile t of a z-chunk -> tile coordinates. With strip_w > 0 tiles are numbered in vertical

@@ -104,6 +104,8 @@ CASES = [
     ("ragged_gauss2", (19, 17, 23), F.GAUSS, 2),
     ("small8_box4", (8, 8, 8), F.BOX, 4),
     ("ragged_box8", (21, 30, 37), F.BOX, 8),
+    ("ragged_box10_tall", (37, 61, 35), F.BOX, 10),
+    ("ragged_box16_tall", (41, 57, 34), F.BOX, 16),
     ("gauss4_40", (40, 36, 33), F.GAUSS, 4),
 ]
 
