@@ -178,10 +178,11 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
       ldoff[i] = 0;
     }
   }
-  // inputs of the arriving plane (pn) and of the plane leaving the window (po); the plane's
-  // base addresses are uniform, so each load is a scalar base plus this thread's offset
+  // inputs of the arriving plane (pn) and of the plane leaving the window (po), raw-point
+  // groups i0 .. i1 - 1; the plane's base addresses are uniform, so each load is a scalar
+  // base plus this thread's offset
   float pn[NPF][4], po[NPF][4];
-  auto load = [&](float (&pf)[NPF][4], int za) {
+  auto load = [&](float (&pf)[NPF][4], int za, int i0, int i1) {
     const int64_t zoff = (int64_t)wrapi(za, A.nz) * plane;
     const char* b0 = reinterpret_cast<const char*>(A.rho + zoff);
     const char* b1 = reinterpret_cast<const char*>(A.u + zoff);
@@ -189,7 +190,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
     const char* b3 = reinterpret_cast<const char*>(A.u + 2 * ntot + zoff);
 #pragma unroll
     for (int i = 0; i < NPF; ++i) {
-      if (has[i]) {
+      if (i >= i0 && i < i1 && has[i]) {
         // opaque here, so that the 32-bit offset is not widened once outside the loop
         // (which would cost a 64-bit address add per load instead of the scalar-base form)
         uint32_t o = pfoff[i];
@@ -201,7 +202,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
       }
     }
   };
-  load(pn, za0);
+  load(pn, za0, 0, NPF);
 
   const bool col_thread = tid < kBN;
   const int col = col_thread ? tid : 0;
@@ -243,10 +244,6 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         }
       }
       __syncthreads();
-      if (k + 1 < nfilt) {
-        load(pn, za + 1);
-        if (k + 1 >= 2 * R) load(po, za + 1 - 2 * R);
-      }
       // ---- x pass, in place: one (quantity, row) per task
       for (int t = tid; t < 10 * HY; t += kBT) {
         T* v = buf + t * HXP;
@@ -255,6 +252,10 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         for (int i = 0; i < HX; ++i) vr[i] = v[i];
         trap_row<R, kBX>(vr, [&](int o, T x) { v[o] = x; });
       }
+      // The next step's inputs are requested in parts between the phases of this step: the
+      // loads of all waves of the CU queue in one vector memory unit, and a burst of them
+      // right after a barrier holds every wave up behind it (a sixth of the time at R = 8).
+      if (k + 1 < nfilt) load(pn, za + 1, 0, 2);
       __syncthreads();
       // ---- y pass: one (quantity, column, half of the rows) per task. In place (short tiles):
       // all reads are done before the barrier, all writes after it; tall tiles write to yb.
@@ -288,6 +289,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
           }
         }
       }
+      if (k + 1 < nfilt) load(pn, za + 1, 2, NPF);
       __syncthreads();
       // ---- z: advance the boxcars; the trapezoid of plane zo = za - R is their mean
       const bool full = k >= 2 * R;
@@ -336,6 +338,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         }
       }
     }
+    if (k + 1 < nfilt && k + 1 >= 2 * R) load(po, za + 1 - 2 * R, 0, NPF);
     // Short tiles, every step: the reads of the y-filtered plane are done before the next
     // staging overwrites it, and the velocity of plane zo is in LDS before the gradient
     // reads it. Tall tiles read only planes of earlier steps here, behind the three barriers
