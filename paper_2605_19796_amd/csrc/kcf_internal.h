@@ -126,7 +126,7 @@ struct MonoArgs {
   int ntx, nty, ntiles;    // output tiles of the x-y pass
   int zs, nzs;             // z slab: planes zs .. zs + nzs - 1
   int nq;                  // quantities kept in the slab buffer
-  void* zbuf;              // z-filtered quantities [nq][nzs][ny][nx], float or double
+  void* zbuf;              // z-filtered quantities [nzs][nq][ny][nx], float or double
   float w[kMaxTaps];       // taps w_{-R..R}
   double wd[kMaxTaps];
   float* f_sgs;            // carrier: [27][N], or NULL

@@ -26,7 +26,8 @@
 //   k_*_z   one thread per (x, y) column and ZT planes: the set's products of the input,
 //           one group of up to nine at a time (k_kc_z: the six rho S_ij, with the x and y
 //           neighbours of each point), filtered along z over a register window of the input
-//           planes and written to the slab buffer [quantities][planes][ny][nx];
+//           planes and written to the slab buffer [planes][quantities][ny][nx] (the
+//           quantities of a plane together: an x-y tile then reads one compact region);
 //   k_*_xy  one workgroup per (tile of 256 points, run of eight planes), XCD-banded: per plane,
 //           the quantities of the tile and its halo staged in LDS G at a time, filtered along
 //           x and y in place, each thread keeping its point's filtered values; then the set's
@@ -421,7 +422,8 @@ __device__ __forceinline__ void z_group(const MonoArgs& A, int grp, int zl0, int
   constexpr int NJ = ZT + 2 * R;  // input planes z0 - R .. z0 + ZT + R - 1 of the window
   constexpr int GS = S::kGS;
   const int64_t plane = (int64_t)A.nx * A.ny;
-  const int64_t qstride = (int64_t)A.nzs * plane;
+  const int64_t qstride = plane;
+  const int64_t pstride = (int64_t)A.nq * plane;
   const T* w = cweights<T>(A);
   T acc[GS][ZT];
 #pragma unroll
@@ -466,7 +468,7 @@ __device__ __forceinline__ void z_group(const MonoArgs& A, int grp, int zl0, int
       T* o = out + (int64_t)qq * qstride;
 #pragma unroll
       for (int k = 0; k < ZT; ++k)
-        if (k < nk) o[(int64_t)k * plane] = acc[q][k];
+        if (k < nk) o[(int64_t)k * pstride] = acc[q][k];
     }
   }
 }
@@ -481,7 +483,7 @@ __device__ __forceinline__ void z_pass(const MonoArgs& A) {
   const int nk = min(ZT, A.nzs - zl0);
   const int64_t plane = (int64_t)A.nx * A.ny;
   const uint32_t cb = (uint32_t)(y * A.nx + x) * (uint32_t)sizeof(float);
-  T* out = reinterpret_cast<T*>(A.zbuf) + (int64_t)zl0 * plane + (int64_t)y * A.nx + x;
+  T* out = reinterpret_cast<T*>(A.zbuf) + (int64_t)zl0 * A.nq * plane + (int64_t)y * A.nx + x;
   if constexpr (S::kStaticGroups) {
     static_assert(S::kGroups == 2, "static groups are unrolled for two groups");
     z_group<S, R, T, 0>(A, 0, zl0, nk, cb, out);
@@ -509,7 +511,8 @@ __device__ __forceinline__ void z_pass_kc(const MonoArgs& A) {
   const int zl0 = blockIdx.z * ZT;
   const int nk = min(ZT, A.nzs - zl0);
   const int64_t plane = (int64_t)A.nx * A.ny;
-  const int64_t qstride = (int64_t)A.nzs * plane;
+  const int64_t qstride = plane;
+  const int64_t pstride = (int64_t)A.nq * plane;
   const int64_t nb = A.ntot * (int64_t)sizeof(float);
   // byte offsets within a plane (< 2^32): the column and its four neighbours
   const uint32_t c0 = (uint32_t)(y * A.nx + x) * 4u;
@@ -584,13 +587,13 @@ __device__ __forceinline__ void z_pass_kc(const MonoArgs& A) {
     P0 = Pp;
     Pp = Pn;
   }
-  T* out = reinterpret_cast<T*>(A.zbuf) + (int64_t)zl0 * plane + (int64_t)y * A.nx + x;
+  T* out = reinterpret_cast<T*>(A.zbuf) + (int64_t)zl0 * pstride + (int64_t)y * A.nx + x;
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     T* o = out + (int64_t)q * qstride;
 #pragma unroll
     for (int k = 0; k < ZT; ++k)
-      if (k < nk) o[(int64_t)k * plane] = acc[q][k];
+      if (k < nk) o[(int64_t)k * pstride] = acc[q][k];
   }
 }
 
@@ -640,14 +643,14 @@ __device__ __forceinline__ void xy_pass(const MonoArgs& A) {
   const int x0 = (tile % A.ntx) * kTX, y0 = (tile / A.ntx) * kTY;
   const int tid = threadIdx.x, px = tid % kTX, py = tid / kTX;
   const int64_t plane = (int64_t)A.nx * A.ny;
-  const int64_t qstride = (int64_t)A.nzs * plane;
+  const int64_t qstride = plane;
   const T* w = cweights<T>(A);
   const bool valid = x0 + px < A.nx && y0 + py < A.ny;
   typename S::Acc acc;  // this thread's FP64 sums over its points
   acc.zero();
   const int z_hi = min((zc + 1) * kXZ, A.nzs);
   for (int zl = zc * kXZ; zl < z_hi; ++zl) {
-    const T* zb = reinterpret_cast<const T*>(A.zbuf) + (int64_t)zl * plane;
+    const T* zb = reinterpret_cast<const T*>(A.zbuf) + (int64_t)zl * A.nq * plane;
     T M[NQ];
 #pragma unroll
     for (int g0 = 0; g0 < NQ; g0 += G) {
@@ -657,9 +660,16 @@ __device__ __forceinline__ void xy_pass(const MonoArgs& A) {
         const int hx = r % HX, hy = r / HX;
         const int64_t o = (int64_t)wrapi(y0 - R + hy, A.ny) * A.nx + wrapi(x0 - R + hx, A.nx);
         T* d = buf + hy * HXP + hx;
+        // every load of the round is issued before the first store (a load that depends on
+        // the run-time count ng would be waited for one at a time); past ng, quantity g0 is
+        // read again and not stored
+        T v[G];
 #pragma unroll
         for (int q = 0; q < G; ++q)
-          if (g0 + q < NQ && q < ng) d[q * QS] = zb[(int64_t)(g0 + q) * qstride + o];
+          if (g0 + q < NQ) v[q] = zb[(int64_t)(g0 + (q < ng ? q : 0)) * qstride + o];
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+          if (g0 + q < NQ && q < ng) d[q * QS] = v[q];
       }
       __syncthreads();
       // x, in place: one (quantity, row, 16-point segment) per task; the second segment's
