@@ -301,7 +301,11 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         qb[q] = (prev + B[q]) * inv_2n;
       }
       if (full) {  // uniform
-        const double rinv = 1.0 / qb[0];
+        // 1 / rho_bar from the hardware estimate and two Newton steps (within an ulp of
+        // double; the quotient itself is correctly rounded only to float32 in the outputs)
+        double rinv = __builtin_amdgcn_rcp(qb[0]);
+        rinv = fma(rinv, fma(-qb[0], rinv, 1.0), rinv);
+        rinv = fma(rinv, fma(-qb[0], rinv, 1.0), rinv);
         const double uT[3] = {qb[1] * rinv, qb[2] * rinv, qb[3] * rinv};
         const float cur_rb = (float)qb[0];
         float cur_tau[6];

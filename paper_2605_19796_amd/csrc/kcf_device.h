@@ -36,15 +36,22 @@ __device__ __forceinline__ void gm_closure(const WidthArgs& W, float rb, PointOu
   float c = W.gm_coef * rb;
   const int ii[6] = {0, 0, 0, 1, 1, 2};
   const int jj[6] = {0, 1, 2, 1, 2, 2};
+  // one contraction or the other (uniform): the empty asm keeps the compiler from
+  // evaluating both and selecting
+  if (W.gm_form == 0) {
+    __asm__ volatile("");
 #pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int i = ii[s], j = jj[s];
-    float a;
-    if (W.gm_form == 0)
-      a = G[i][0] * G[j][0] + G[i][1] * G[j][1] + G[i][2] * G[j][2];
-    else
-      a = G[0][i] * G[0][j] + G[1][i] * G[1][j] + G[2][i] * G[2][j];
-    P.tgm[s] = c * a;
+    for (int s = 0; s < 6; ++s) {
+      const int i = ii[s], j = jj[s];
+      P.tgm[s] = c * (G[i][0] * G[j][0] + G[i][1] * G[j][1] + G[i][2] * G[j][2]);
+    }
+  } else {
+    __asm__ volatile("");
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int i = ii[s], j = jj[s];
+      P.tgm[s] = c * (G[0][i] * G[0][j] + G[1][i] * G[1][j] + G[2][i] * G[2][j]);
+    }
   }
 }
 
@@ -63,7 +70,9 @@ __device__ __forceinline__ void smag_closure(const WidthArgs& W, float rb, Point
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) ss += S[i][j] * S[i][j];
-  const float smag = sqrtf(2.f * ss);
+  // the hardware square root (within 1 ulp): a correctly rounded one costs about ten more
+  // instructions per point, far below the closure's own accuracy
+  const float smag = __builtin_amdgcn_sqrtf(2.f * ss);
   const float trs = (S[0][0] + S[1][1] + S[2][2]) * (1.f / 3.f);
   const float cs = -2.f * rb * W.smag_coef * smag;
 #pragma unroll
@@ -97,8 +106,9 @@ __device__ __forceinline__ void point_closures(const WidthArgs& W, float rb, con
 
 // What one point contributes to the FP64 sums. Products of two float32 values are exact in
 // double, so every contribution is formed in double from the stored float outputs. Points
-// outside the interior or with a non-finite value contribute zeros: their inputs are replaced
-// by zero here, before any product is formed, so no NaN reaches a sum.
+// outside the interior or with a non-finite value (use false) contribute nothing: the lane
+// fold replaces their inputs by zero before any product is formed, the per-lane sums skip
+// them, so no NaN reaches a sum.
 struct StatIn {
   float rb, tau[6], tgm[6];
   double ke, pi, pigm, pism;
@@ -128,16 +138,33 @@ __device__ __forceinline__ void stat_inputs(float rb, const float (&u)[3], const
   const bool use = valid && fin;
   I.bad = valid && !fin;
   I.use = use;
-  I.rb = use ? rb : 0.f;
-  I.ke = use ? ke : 0.0;
-  I.pi = use ? pi : 0.0;
-  I.pigm = use ? pigm : 0.0;
-  I.pism = use ? pism : 0.0;
+  I.rb = rb;
+  I.ke = ke;
+  I.pi = pi;
+  I.pigm = pigm;
+  I.pism = pism;
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
-    I.tau[s] = use ? tau[s] : 0.f;
-    I.tgm[s] = use ? P.tgm[s] : 0.f;
+    I.tau[s] = tau[s];
+    I.tgm[s] = P.tgm[s];
   }
+}
+
+// The inputs of a point that is not used replaced by zero.
+__device__ __forceinline__ StatIn stat_masked(const StatIn& I) {
+  StatIn J = I;
+  const bool use = I.use;
+  J.rb = use ? I.rb : 0.f;
+  J.ke = use ? I.ke : 0.0;
+  J.pi = use ? I.pi : 0.0;
+  J.pigm = use ? I.pigm : 0.0;
+  J.pism = use ? I.pism : 0.0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    J.tau[s] = use ? I.tau[s] : 0.f;
+    J.tgm[s] = use ? I.tgm[s] : 0.f;
+  }
+  return J;
 }
 
 // Contribution to slot s (s is a compile-time constant after unrolling).
@@ -221,7 +248,8 @@ __device__ __forceinline__ void stat_fold(const V& val, StatAcc& a) {
 }
 
 __device__ __forceinline__ void stat_add(const StatIn& I, StatAcc& a) {
-  stat_fold([&](int s) { return stat_val(I, s); }, a);
+  const StatIn J = stat_masked(I);  // every lane takes part in the fold
+  stat_fold([&](int s) { return stat_val(J, s); }, a);
 }
 
 // Wave totals: the 16-lane reduction of every accumulator, then lanes 0, 16, 32 and 48
@@ -258,8 +286,12 @@ __device__ __forceinline__ void stat_zero(StatLane& a) {
 }
 
 __device__ __forceinline__ void stat_add(const StatIn& I, StatLane& a) {
+  if (I.use) {  // lanes of points not used skip the additions
 #pragma unroll
-  for (int k = 0; k < kNStat; ++k) a.s[k] += stat_val(I, k);
+    for (int k = 0; k < kNStat; ++k)
+      if (k != S_NONFINITE) a.s[k] += stat_val(I, k);
+  }
+  if (I.bad) a.s[S_NONFINITE] += 1.0;
 }
 
 __device__ __forceinline__ void write_stats(double* part, const StatLane& a) {
