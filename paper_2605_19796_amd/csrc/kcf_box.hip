@@ -225,6 +225,26 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
     const int za = za0 + k;
     const int zo = za - R;
     const int us = (k - 2 * R + NSU) % NSU;  // ut slot of plane zo
+    // tall tiles store the Favre fields of plane zo at the end of the step, after the
+    // gradient epilogue, when the vector memory path is idle (its loads and these stores
+    // are the CU's busiest shared resource); short tiles store them at once
+    bool st_do = false;
+    float st_rb = 0.f, st_u[3] = {0.f, 0.f, 0.f}, st_tau[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    auto store_fields = [&](bool on, float rb_v, const float (&u_v)[3], const float (&t_v)[6]) {
+      if (!on) return;
+      const int64_t zb = (int64_t)zo * plane;
+      uint32_t o = cofs;
+      __asm__ volatile("" : "+v"(o));  // keeps the scalar-base store form (see load)
+      if (W.rho_bar) *plane_addr(W.rho_bar, 0, ntot, zb, o) = rb_v;
+      if (W.ut) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) *plane_addr(W.ut, i, ntot, zb, o) = u_v[i];
+      }
+      if (W.tau) {
+#pragma unroll
+        for (int s = 0; s < 6; ++s) *plane_addr(W.tau, s, ntot, zb, o) = t_v[s];
+      }
+    };
     if (k < nfilt) {  // uniform
       const bool leaving = k >= 2 * R;  // uniform: plane za - 2R is inside the window
       // ---- staging: product differences of plane za
@@ -326,19 +346,17 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
 #pragma unroll
           for (int s = 0; s < 6; ++s) lg[(1 + s) * NI] = cur_tau[s];
         }
-        if (interior && zo >= z0 && zo < z1) {
-          const int64_t zb = (int64_t)zo * plane;
-          uint32_t o = cofs;
-          __asm__ volatile("" : "+v"(o));  // keeps the scalar-base store form (see load)
-          if (W.rho_bar) *plane_addr(W.rho_bar, 0, ntot, zb, o) = cur_rb;
-          if (W.ut) {
+        const bool on = interior && zo >= z0 && zo < z1;
+        const float cur_u[3] = {(float)uT[0], (float)uT[1], (float)uT[2]};
+        if (kSplit) {
+          st_do = on;
+          st_rb = cur_rb;
 #pragma unroll
-            for (int i = 0; i < 3; ++i) *plane_addr(W.ut, i, ntot, zb, o) = (float)uT[i];
-          }
-          if (W.tau) {
+          for (int i = 0; i < 3; ++i) st_u[i] = cur_u[i];
 #pragma unroll
-            for (int s = 0; s < 6; ++s) *plane_addr(W.tau, s, ntot, zb, o) = cur_tau[s];
-          }
+          for (int s = 0; s < 6; ++s) st_tau[s] = cur_tau[s];
+        } else {
+          store_fields(on, cur_rb, cur_u, cur_tau);
         }
       }
     }
@@ -389,6 +407,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         stat_add(I, acc);
       }
     }
+    if (kSplit) store_fields(st_do, st_rb, st_u, st_tau);
   }
   if (W.partials) write_stats(W.partials + ((int64_t)item * (kBT / 64) + (tid >> 6)) * kNStat, acc);
 }
