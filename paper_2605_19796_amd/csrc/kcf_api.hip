@@ -15,6 +15,7 @@ struct kcf_ctx {
   double* d_part = nullptr;   // FP64 partial sums of the kernels
   size_t part_cap = 0;        // doubles
   double* d_sums = nullptr;   // reduced sums (device)
+  double* d_red = nullptr;    // chunk totals of the reductions (kRedBlocks x kNStat)
   double* h_sums = nullptr;   // reduced sums (pinned host)
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop) of timed launches
@@ -188,7 +189,8 @@ void derive_stats(const double* raw, double delta, double m2, kcf_width_stats* s
 }
 
 int reduce_to_host(kcf_ctx* c, int nparts, int nstat, int slot) {
-  hipError_t e = launch_reduce(c->d_part, nparts, nstat, c->d_sums + slot * kNStat, c->stream);
+  hipError_t e = launch_reduce(c->d_part, nparts, nstat, c->d_sums + slot * kNStat, c->d_red,
+                               c->stream);
   if (e != hipSuccess) return hip_fail(e, "reduce launch");
   return KCF_OK;
 }
@@ -300,7 +302,7 @@ int run_monomials(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, in
     if ((rc = timed_end(c))) return rc;
   }
   if (stats) {
-    hipError_t e = launch_reduce(c->d_part, (int)nrec, nstat, c->d_sums, c->stream);
+    hipError_t e = launch_reduce(c->d_part, (int)nrec, nstat, c->d_sums, c->d_red, c->stream);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
     KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * nstat, hipMemcpyDeviceToHost,
                            c->stream), "stats copy");
@@ -334,6 +336,7 @@ int kcf_ctx_create(kcf_ctx** out, int device, void* stream) {
   c->device = device;
   c->stream = (hipStream_t)stream;
   if (hipMalloc(&c->d_sums, kSumCap * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->d_red, (size_t)kRedBlocks * kNStat * sizeof(double)) != hipSuccess ||
       hipHostMalloc(&c->h_sums, kSumCap * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     kcf_ctx_destroy(c);
     return fail(KCF_ENOMEM, "cannot allocate statistics buffers");
@@ -358,6 +361,7 @@ void kcf_ctx_destroy(kcf_ctx* c) {
   if (c->d_fld) hipFree(c->d_fld);
   if (c->d_kc) hipFree(c->d_kc);
   if (c->d_sums) hipFree(c->d_sums);
+  if (c->d_red) hipFree(c->d_red);
   if (c->h_sums) hipHostFree(c->h_sums);
   for (hipEvent_t e : c->ev) hipEventDestroy(e);
   delete c;
@@ -580,7 +584,7 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
   if (stats) {
     for (int f = 0; f < nf; ++f) {
       hipError_t e = launch_reduce(c->d_part + part_off[f], nparts[f], kNStat,
-                                   c->d_sums + f * kNStat, c->stream);
+                                   c->d_sums + f * kNStat, c->d_red, c->stream);
       if (e != hipSuccess) return hip_fail(e, "reduce launch");
     }
     KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * kNStat * nf,
@@ -797,7 +801,7 @@ int kcf_input_stats(kcf_ctx* c, const kcf_grid* grid, const float* rho, const fl
   S.partials = c->d_part;
   hipError_t e = launch_input_stats(S, c->stream);
   if (e != hipSuccess) return hip_fail(e, "input stats launch");
-  e = launch_reduce(c->d_part, (int)nrec, 4, c->d_sums, c->stream);
+  e = launch_reduce(c->d_part, (int)nrec, 4, c->d_sums, c->d_red, c->stream);
   if (e != hipSuccess) return hip_fail(e, "reduce launch");
   KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * 4, hipMemcpyDeviceToHost,
                          c->stream), "stats copy");
@@ -820,7 +824,7 @@ int kcf_reduce_check(kcf_ctx* c, const float* a, const float* b, int64_t n, doub
   if (rc) return rc;
   hipError_t e = launch_reduce_check(a, b, n, c->d_part, (int)nb, c->stream);
   if (e != hipSuccess) return hip_fail(e, "reduce launch");
-  e = launch_reduce(c->d_part, (int)nb * 4, 3, c->d_sums, c->stream);
+  e = launch_reduce(c->d_part, (int)nb * 4, 3, c->d_sums, c->d_red, c->stream);
   if (e != hipSuccess) return hip_fail(e, "reduce launch");
   KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * 3, hipMemcpyDeviceToHost,
                          c->stream), "copy");

@@ -179,19 +179,36 @@ __global__ void __launch_bounds__(kIX) k_input_stats(InputStatArgs S) {
 }
 
 // ---------------------------------------------------------------- FP64 partial sums
-__global__ void __launch_bounds__(256) k_reduce(const double* __restrict__ part, int nparts,
-                                                int nstat, double* __restrict__ out) {
+// Records of nstat sums, reduced in two fixed-order passes (deterministic): each of up to
+// kRedBlocks workgroups sums a contiguous chunk of records, 256 / nstat threads per sum
+// reading neighbouring statistics of a record together; one workgroup then sums the chunk
+// totals in chunk order.
+__global__ void __launch_bounds__(256) k_reduce_part(const double* __restrict__ part, int nparts,
+                                                     int nstat, int chunk,
+                                                     double* __restrict__ red) {
   __shared__ double sh[256];
-  const int s = blockIdx.x;
+  const int G = 256 / nstat;  // threads per statistic
+  const int t = threadIdx.x, s = t % nstat, g = t / nstat;
+  const int r0 = blockIdx.x * chunk, r1 = min(r0 + chunk, nparts);
   double a = 0;
-  for (int p = threadIdx.x; p < nparts; p += 256) a += part[(int64_t)p * nstat + s];
-  sh[threadIdx.x] = a;
+  if (g < G)
+    for (int r = r0 + g; r < r1; r += G) a += part[(int64_t)r * nstat + s];
+  sh[t] = a;
   __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
+  if (t < nstat) {
+    double b = 0;
+    for (int k = 0; k < G; ++k) b += sh[k * nstat + t];
+    red[(int64_t)blockIdx.x * nstat + t] = b;
   }
-  if (threadIdx.x == 0) out[s] = sh[0];
+}
+
+__global__ void __launch_bounds__(64) k_reduce_final(const double* __restrict__ red, int nblocks,
+                                                     int nstat, double* __restrict__ out) {
+  for (int s = threadIdx.x; s < nstat; s += 64) {
+    double b = 0;
+    for (int k = 0; k < nblocks; ++k) b += red[(int64_t)k * nstat + s];
+    out[s] = b;
+  }
 }
 
 constexpr int kCT = 256;  // threads of the reduction-check kernel
@@ -244,8 +261,16 @@ hipError_t launch_input_stats(const InputStatArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_reduce(const double* partials, int nparts, int nstat, double* out,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(nstat), dim3(256), 0, s, partials, nparts, nstat, out);
+                         double* scratch, hipStream_t s) {
+  if (nstat < 1 || nstat > 256 || nparts < 0) return hipErrorInvalidValue;
+  int nb = (nparts + 63) / 64;
+  nb = nb < 1 ? 1 : (nb > kRedBlocks ? kRedBlocks : nb);
+  const int chunk = (nparts + nb - 1) / nb;
+  hipLaunchKernelGGL(k_reduce_part, dim3(nb), dim3(256), 0, s, partials, nparts, nstat, chunk,
+                     scratch);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, scratch, nb, nstat, out);
   return hipGetLastError();
 }
 
