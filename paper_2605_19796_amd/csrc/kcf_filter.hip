@@ -85,7 +85,8 @@ __global__ void __launch_bounds__(kGX) k_grad_closure(ClosureArgs C) {
 // E_k, enstrophy (sixth-order central vorticity) and <rho> of the unfiltered input. A block
 // owns kIX consecutive points of one x-row and kIZ planes; each thread marches along z with
 // the seven planes of u_x and u_y that the z-derivatives need held in registers, and reads
-// the x and y neighbours of its plane through the caches.
+// the x and y neighbours of its plane through the caches, one plane ahead of their use, as
+// a uniform plane base plus 32-bit offsets.
 constexpr int kIX = 128, kIZ = 16;
 
 __device__ __forceinline__ double d6(float p1, float p2, float p3, float m1, float m2, float m3) {
@@ -101,50 +102,70 @@ __global__ void __launch_bounds__(kIX) k_input_stats(InputStatArgs S) {
   const bool valid = x < S.nx;
   const int xc = valid ? x : 0;
   const int64_t plane = (int64_t)S.nx * S.ny;
-  const int64_t row = (int64_t)y * S.nx;
+  // byte offsets within a plane (below 2^32): the column, its y neighbours y +- 1..3 and its
+  // x neighbours x +- 1..3 (periodic)
+  const uint32_t own = (uint32_t)(y * S.nx + xc) * 4u;
+  uint32_t oy[6], ox[6];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    oy[m] = (uint32_t)(wrapi(y + m + 1, S.ny) * S.nx + xc) * 4u;
+    oy[m + 3] = (uint32_t)(wrapi(y - m - 1, S.ny) * S.nx + xc) * 4u;
+    ox[m] = (uint32_t)(y * S.nx + wrapi(xc + m + 1, S.nx)) * 4u;
+    ox[m + 3] = (uint32_t)(y * S.nx + wrapi(xc - m - 1, S.nx)) * 4u;
+  }
   const float* ux = S.u;
   const float* uy = S.u + S.ntot;
   const float* uz = S.u + 2 * S.ntot;
-  int xo[6];      // x + 1, x + 2, x + 3, x - 1, x - 2, x - 3 (periodic)
-  int64_t yo[6];  // the same rows, as offsets
-#pragma unroll
-  for (int m = 0; m < 3; ++m) {
-    xo[m] = wrapi(xc + m + 1, S.nx);
-    xo[m + 3] = wrapi(xc - m - 1, S.nx);
-    yo[m] = (int64_t)wrapi(y + m + 1, S.ny) * S.nx;
-    yo[m + 3] = (int64_t)wrapi(y - m - 1, S.ny) * S.nx;
-  }
+  auto at = [](const float* base, int64_t zoff, uint32_t o) {
+    __asm__ volatile("" : "+v"(o));  // keeps the 32-bit offset form of the load
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base + zoff) + o);
+  };
   float wx[7], wy[7];  // u_x, u_y at planes z - 3 .. z + 3
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
-    const int64_t g = (int64_t)wrapi(z0 - 3 + m, S.nz) * plane + row + xc;
-    wx[m] = ux[g];
-    wy[m] = uy[g];
+    const int64_t zoff = (int64_t)wrapi(z0 - 3 + m, S.nz) * plane;
+    wx[m] = at(ux, zoff, own);
+    wy[m] = at(uy, zoff, own);
   }
+  // values of one plane: z-window entry, y and x neighbours, rho and u_z of the column
+  struct Pl { float wx6, wy6, zy[6], xy[6], zx[6], yx[6], r, vz; };
+  auto fetch = [&](int z, Pl& P) {
+    const int64_t zp = (int64_t)wrapi(z + 3, S.nz) * plane;
+    P.wx6 = at(ux, zp, own);
+    P.wy6 = at(uy, zp, own);
+    const int64_t zb = (int64_t)z * plane;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      P.zy[m] = at(uz, zb, oy[m]);
+      P.xy[m] = at(ux, zb, oy[m]);
+      P.zx[m] = at(uz, zb, ox[m]);
+      P.yx[m] = at(uy, zb, ox[m]);
+    }
+    P.r = at(S.rho, zb, own);
+    P.vz = at(uz, zb, own);
+  };
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  Pl P;
+  Pl Q;
+  if (z0 < z1) fetch(z0, Q);
   for (int z = z0; z < z1; ++z) {
-    const int64_t gp = (int64_t)wrapi(z + 3, S.nz) * plane + row + xc;
-    wx[6] = ux[gp];
-    wy[6] = uy[gp];
-    const int64_t base = (int64_t)z * plane;
-    const int64_t g = base + row + xc;
-    const float* pyy = uy + base + row;
-    const float* pzx = uz + base + row;
-    const float* pxb = ux + base + xc;
-    const float* pzb = uz + base + xc;
-    const double dy_uz = d6(pzb[yo[0]], pzb[yo[1]], pzb[yo[2]], pzb[yo[3]], pzb[yo[4]], pzb[yo[5]]);
-    const double dy_ux = d6(pxb[yo[0]], pxb[yo[1]], pxb[yo[2]], pxb[yo[3]], pxb[yo[4]], pxb[yo[5]]);
-    const double dx_uz = d6(pzx[xo[0]], pzx[xo[1]], pzx[xo[2]], pzx[xo[3]], pzx[xo[4]], pzx[xo[5]]);
-    const double dx_uy = d6(pyy[xo[0]], pyy[xo[1]], pyy[xo[2]], pyy[xo[3]], pyy[xo[4]], pyy[xo[5]]);
+    P = Q;
+    if (z + 1 < z1) fetch(z + 1, Q);
+    wx[6] = P.wx6;
+    wy[6] = P.wy6;
+    const double dy_uz = d6(P.zy[0], P.zy[1], P.zy[2], P.zy[3], P.zy[4], P.zy[5]);
+    const double dy_ux = d6(P.xy[0], P.xy[1], P.xy[2], P.xy[3], P.xy[4], P.xy[5]);
+    const double dx_uz = d6(P.zx[0], P.zx[1], P.zx[2], P.zx[3], P.zx[4], P.zx[5]);
+    const double dx_uy = d6(P.yx[0], P.yx[1], P.yx[2], P.yx[3], P.yx[4], P.yx[5]);
     const double dz_uy = d6(wy[4], wy[5], wy[6], wy[2], wy[1], wy[0]);
     const double dz_ux = d6(wx[4], wx[5], wx[6], wx[2], wx[1], wx[0]);
-    const double ox = (dy_uz - dz_uy) * S.inv60h;
-    const double oy = (dz_ux - dx_uz) * S.inv60h;
-    const double oz = (dx_uy - dy_ux) * S.inv60h;
-    const double r = S.rho[g];
-    const double vx = wx[3], vy = wy[3], vz = uz[g];
+    const double ox_ = (dy_uz - dz_uy) * S.inv60h;
+    const double oy_ = (dz_ux - dx_uz) * S.inv60h;
+    const double oz_ = (dx_uy - dy_ux) * S.inv60h;
+    const double r = P.r;
+    const double vx = wx[3], vy = wy[3], vz = P.vz;
     const double ek = 0.5 * r * (vx * vx + vy * vy + vz * vz);
-    const double en = 0.5 * (ox * ox + oy * oy + oz * oz);
+    const double en = 0.5 * (ox_ * ox_ + oy_ * oy_ + oz_ * oz_);
     if (valid) {
       if (isfinite(ek + en + r)) {
         a0 += r;
