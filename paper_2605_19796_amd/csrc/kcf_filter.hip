@@ -223,12 +223,20 @@ __global__ void __launch_bounds__(256) k_reduce_part(const double* __restrict__ 
   }
 }
 
-__global__ void __launch_bounds__(64) k_reduce_final(const double* __restrict__ red, int nblocks,
-                                                     int nstat, double* __restrict__ out) {
-  for (int s = threadIdx.x; s < nstat; s += 64) {
+// One thread per chunk brings its totals into LDS in one round of loads; then one thread per
+// statistic adds them up in chunk order.
+__global__ void __launch_bounds__(kRedBlocks) k_reduce_final(const double* __restrict__ red,
+                                                             int nblocks, int nstat,
+                                                             double* __restrict__ out) {
+  __shared__ double sh[kNStat * kRedBlocks];
+  const int t = threadIdx.x;
+  if (t < nblocks)
+    for (int s = 0; s < nstat; ++s) sh[s * kRedBlocks + t] = red[(int64_t)t * nstat + s];
+  __syncthreads();
+  if (t < nstat) {
     double b = 0;
-    for (int k = 0; k < nblocks; ++k) b += red[(int64_t)k * nstat + s];
-    out[s] = b;
+    for (int k = 0; k < nblocks; ++k) b += sh[t * kRedBlocks + k];
+    out[t] = b;
   }
 }
 
@@ -283,7 +291,7 @@ hipError_t launch_input_stats(const InputStatArgs& a, hipStream_t s) {
 
 hipError_t launch_reduce(const double* partials, int nparts, int nstat, double* out,
                          double* scratch, hipStream_t s) {
-  if (nstat < 1 || nstat > 256 || nparts < 0) return hipErrorInvalidValue;
+  if (nstat < 1 || nstat > kNStat || nparts < 0) return hipErrorInvalidValue;
   int nb = (nparts + 63) / 64;
   nb = nb < 1 ? 1 : (nb > kRedBlocks ? kRedBlocks : nb);
   const int chunk = (nparts + nb - 1) / nb;
@@ -291,7 +299,7 @@ hipError_t launch_reduce(const double* partials, int nparts, int nstat, double* 
                      scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(64), 0, s, scratch, nb, nstat, out);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kRedBlocks), 0, s, scratch, nb, nstat, out);
   return hipGetLastError();
 }
 

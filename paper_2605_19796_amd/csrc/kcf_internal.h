@@ -92,8 +92,8 @@ int64_t grad_closure_records(const ClosureArgs& a);  // per-wave partial records
 hipError_t launch_grad_closure(const ClosureArgs& a, hipStream_t s);
 int64_t input_stats_records(const InputStatArgs& a);  // per-wave partial records
 hipError_t launch_input_stats(const InputStatArgs& a, hipStream_t s);
-// Sums of nparts records of nstat (<= 256) doubles into out; scratch holds kRedBlocks * nstat
-// doubles of chunk totals.
+// Sums of nparts records of nstat (<= kNStat) doubles into out; scratch holds
+// kRedBlocks * nstat doubles of chunk totals.
 constexpr int kRedBlocks = 256;
 hipError_t launch_reduce(const double* partials, int nparts, int nstat, double* out,
                          double* scratch, hipStream_t s);
