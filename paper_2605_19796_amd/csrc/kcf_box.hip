@@ -412,14 +412,19 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   if (W.partials) write_stats(W.partials + ((int64_t)item * (kBT / 64) + (tid >> 6)) * kNStat, acc);
 }
 
-template <int R, typename T>
+template <int R, typename T, bool kOpt>
 __global__ void __launch_bounds__(TileFor<R>::BT)
     __attribute__((amdgpu_waves_per_eu(box_waves<R, T>(), box_waves<R, T>())))
     k_box1(FilterArgs A) {
   __shared__ double smem[BoxLds<R, T>::doubles];
   int item;
   if (!map_block(A, item)) return;
-  box_body<R, T>(A, A.wa, item, reinterpret_cast<unsigned char*>(smem));
+  // without optional gradient-epilogue outputs their stores and the KC scalars compile away
+  WidthArgs W = A.wa;
+  if constexpr (!kOpt) {
+    W.grad = W.tau_gm = W.tau_smag = W.k_sgs = W.nu_t = W.omega_t = W.q_crit = nullptr;
+  }
+  box_body<R, T>(A, W, item, reinterpret_cast<unsigned char*>(smem));
 }
 
 template <int R, typename T>
@@ -430,7 +435,11 @@ BoxGeom geom_of() {
 
 template <int R, typename T>
 hipError_t launch_of(const FilterArgs& a, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_box1<R, T>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
+  const WidthArgs& w = a.wa;
+  if (w.grad || w.tau_gm || w.tau_smag || w.k_sgs || w.nu_t || w.omega_t || w.q_crit)
+    hipLaunchKernelGGL((k_box1<R, T, true>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_box1<R, T, false>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
   return hipGetLastError();
 }
 

@@ -175,6 +175,24 @@ def test_fields_without_statistics(ctx, kind, nd):
         assert np.array_equal(outs[0][f].cpu().numpy(), full[0][f]), f
 
 
+@pytest.mark.parametrize("nd", [2, 8, 16])
+def test_statistics_with_favre_fields_only(ctx, nd):
+    """The call that stores only the Favre fields and reduces the statistics (the launch the
+    four-width benchmark times) gives the fields and the FP64 sums of the call that also
+    stores every optional output, bit for bit, and the oracle's statistics."""
+    say(f"[gpu] statistics with the Favre fields only, box n={nd}")
+    rho, u = synth.workload_fields("c512_box_multi", n=40)
+    rho, u = rho.numpy(), u.numpy()
+    h = 2 * math.pi / 40
+    full, st_full = run_gpu(ctx, rho, u, h, [(F.BOX, nd)])
+    fields = ("rho_bar", "ut", "tau")
+    part, st_part = run_gpu(ctx, rho, u, h, [(F.BOX, nd)], fields=fields)
+    for f in fields:
+        assert np.array_equal(part[0][f], full[0][f]), f
+    assert st_part[0]["raw"] == st_full[0]["raw"]
+    check_stats(st_part[0], F.full_path(rho, u, F.BOX, nd, h))
+
+
 @pytest.mark.parametrize("cp", [dict(gm_form=1), dict(m2_mode=1), dict(ksgs_rho_ref=1),
                                 dict(nu_mol=0.002, theta=1.0 / 3.0, dt=1.0, c_s=0.105, c_nu=0.035)])
 def test_closure_variants(ctx, cp):
