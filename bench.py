@@ -45,8 +45,8 @@ BYTES_PER_POINT = 16 + 40  # one width: read rho, u; write rho_bar, ut, tau
 WIDTHS = (2, 4, 8, 16)
 # kernel instance each width launches in the timed step (radius n/2; FP64 sums up to 4h;
 # Favre fields and statistics, no optional gradient-epilogue outputs)
-KERNELS = {2: "k_box1<1, double, false>", 4: "k_box1<2, double, false>",
-           8: "k_box1<4, float, false>", 16: "k_box1<8, float, false>"}
+KERNELS = {2: "k_box1<1, double, 0>", 4: "k_box1<2, double, 0>",
+           8: "k_box1<4, float, 0>", 16: "k_box1<8, float, 0>"}
 KERNEL_SOURCES = ("kcf_box.hip", "kcf_device.h", "kcf_internal.h")
 COPY_BYTES = 1 << 31  # plain copy for counter calibration: 2 GiB read, 2 GiB written
 

@@ -412,18 +412,19 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   if (W.partials) write_stats(W.partials + ((int64_t)item * (kBT / 64) + (tid >> 6)) * kNStat, acc);
 }
 
-template <int R, typename T, bool kOpt>
+// kOut: which optional gradient-epilogue outputs the call can store (0: none, 1: the gradient
+// and Q only, 2: any); the others, their stores and (below 2) the KC scalars compile away,
+// which also keeps the kernel's scalar registers from spilling
+template <int R, typename T, int kOut>
 __global__ void __launch_bounds__(TileFor<R>::BT)
     __attribute__((amdgpu_waves_per_eu(box_waves<R, T>(), box_waves<R, T>())))
     k_box1(FilterArgs A) {
   __shared__ double smem[BoxLds<R, T>::doubles];
   int item;
   if (!map_block(A, item)) return;
-  // without optional gradient-epilogue outputs their stores and the KC scalars compile away
   WidthArgs W = A.wa;
-  if constexpr (!kOpt) {
-    W.grad = W.tau_gm = W.tau_smag = W.k_sgs = W.nu_t = W.omega_t = W.q_crit = nullptr;
-  }
+  if constexpr (kOut < 2) W.tau_gm = W.tau_smag = W.k_sgs = W.nu_t = W.omega_t = nullptr;
+  if constexpr (kOut < 1) W.grad = W.q_crit = nullptr;
   box_body<R, T>(A, W, item, reinterpret_cast<unsigned char*>(smem));
 }
 
@@ -436,10 +437,12 @@ BoxGeom geom_of() {
 template <int R, typename T>
 hipError_t launch_of(const FilterArgs& a, int nblocks, hipStream_t s) {
   const WidthArgs& w = a.wa;
-  if (w.grad || w.tau_gm || w.tau_smag || w.k_sgs || w.nu_t || w.omega_t || w.q_crit)
-    hipLaunchKernelGGL((k_box1<R, T, true>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
+  if (w.tau_gm || w.tau_smag || w.k_sgs || w.nu_t || w.omega_t)
+    hipLaunchKernelGGL((k_box1<R, T, 2>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
+  else if (w.grad || w.q_crit)
+    hipLaunchKernelGGL((k_box1<R, T, 1>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_box1<R, T, false>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
+    hipLaunchKernelGGL((k_box1<R, T, 0>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
   return hipGetLastError();
 }
 

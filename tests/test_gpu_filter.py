@@ -176,16 +176,17 @@ def test_fields_without_statistics(ctx, kind, nd):
 
 
 @pytest.mark.parametrize("nd", [2, 8, 16])
-def test_statistics_with_favre_fields_only(ctx, nd):
-    """The call that stores only the Favre fields and reduces the statistics (the launch the
-    four-width benchmark times) gives the fields and the FP64 sums of the call that also
-    stores every optional output, bit for bit, and the oracle's statistics."""
-    say(f"[gpu] statistics with the Favre fields only, box n={nd}")
+@pytest.mark.parametrize("fields", [("rho_bar", "ut", "tau"), ("rho_bar", "ut", "tau", "grad")])
+def test_statistics_with_fewer_outputs(ctx, nd, fields):
+    """The calls that store only the Favre fields (the launch the four-width benchmark times),
+    or those and the gradient, run kernels compiled without the other optional outputs; they
+    give the fields and the FP64 sums of the call that stores every output, bit for bit, and
+    the oracle's statistics."""
+    say(f"[gpu] statistics with outputs {fields}, box n={nd}")
     rho, u = synth.workload_fields("c512_box_multi", n=40)
     rho, u = rho.numpy(), u.numpy()
     h = 2 * math.pi / 40
     full, st_full = run_gpu(ctx, rho, u, h, [(F.BOX, nd)])
-    fields = ("rho_bar", "ut", "tau")
     part, st_part = run_gpu(ctx, rho, u, h, [(F.BOX, nd)], fields=fields)
     for f in fields:
         assert np.array_equal(part[0][f], full[0][f]), f
