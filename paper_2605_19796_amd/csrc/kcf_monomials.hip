@@ -461,14 +461,19 @@ __device__ __forceinline__ void z_group(const MonoArgs& A, int grp, int zl0, int
       }
     }
   }
+  // strides and count opaque here: the store offsets are formed at the stores instead of
+  // being held in scalar registers through the window loop
+  int64_t qs = qstride, ps = pstride;
+  int nkz = nk;
+  __asm__ volatile("" : "+s"(qs), "+s"(ps), "+s"(nkz));
 #pragma unroll
   for (int q = 0; q < GS; ++q) {
     const int qq = grp * GS + q;
     if (qq < A.nq) {
-      T* o = out + (int64_t)qq * qstride;
+      T* o = out + (int64_t)qq * qs;
 #pragma unroll
       for (int k = 0; k < ZT; ++k)
-        if (k < nk) o[(int64_t)k * pstride] = acc[q][k];
+        if (k < nkz) o[(int64_t)k * ps] = acc[q][k];
     }
   }
 }
