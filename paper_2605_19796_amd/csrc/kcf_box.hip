@@ -1,23 +1,25 @@
 // Box-filter kernels (gfx950): trapezoidal top-hat of width 2R h, all ten filtered quantities
 // of a column in one thread, sliding sums along x and y, a running window sum along z.
 //
-// A workgroup of 256 threads owns an 18x14 column tile (16x12 output columns plus the
-// one-cell halo of the central-difference gradient) and marches along z; two workgroups
-// share a CU, so that one computes while the other waits at a barrier. At step k the
-// plane za = za0 + k arrives:
+// A workgroup owns a tile of columns (the output columns plus the one-cell halo of the
+// central-difference gradient) and marches along z: short tiles (18x14 columns, 256 threads,
+// three workgroups per CU) for R <= 4, tall tiles (18x28, 512 threads, one per CU) beyond.
+// At step k the plane za = za0 + k arrives:
 //   * staging: the inputs of plane za and of plane za - 2R (the one leaving the window; it is
-//     read a second time, from cache) are prefetched one step ahead and turned into the
+//     read a second time, from cache), loaded during the previous step, are turned into the
 //     differences d = P(za) - P(za - 2R) of the ten products P = rho, rho u_i, rho u_i u_j;
-//   * x pass and y pass, in place in one LDS buffer: each task slides a trapezoid window
-//     over one row (column) of one quantity in registers, three operations per output (the
-//     window is formed as the sum of two boxcars, unscaled: each pass multiplies by 2n);
+//   * x pass and y pass through LDS: each task slides a trapezoid window over one row
+//     (column) of one quantity in registers, three operations per output (the window is the
+//     sum of two boxcars, unscaled: each pass multiplies by 2n); the y pass works in place in
+//     short tiles and writes a separate buffer in tall ones;
 //   * z: since the x-y filter is linear, the filtered d is the change of the 2R-plane boxcar
 //     sum B of the filtered products; B is kept per column thread in FP64, and the trapezoid
 //     of plane za - R is the mean of two consecutive boxcars, (B_{k-1} + B_k) / (2n), and
 //     the factors of the x and y passes are divided out with it;
-//   * epilogue: Favre velocity and tau from the FP64 window sums; the velocity of three
-//     planes goes to LDS for the gradient, which is evaluated one plane behind together
-//     with the closures and the FP64 statistics.
+//   * epilogue A: Favre velocity and tau from the FP64 window sums, stored (tall tiles: at
+//     the end of the step), the velocity and rho_bar, tau kept in LDS rings;
+//   * epilogue B: gradient, closures and FP64 statistics of a plane one (short tiles) or two
+//     (tall tiles) planes behind, from the rings.
 // T is the type of the products and of the x-y passes: double for narrow widths, where tau
 // is a small difference of large filtered products, float otherwise. Outputs are float32.
 #include <type_traits>
