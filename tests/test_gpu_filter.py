@@ -291,6 +291,36 @@ def test_input_stats(ctx):
         assert abs(st[k] - o[k]) <= 1e-10 * abs(o[k])
 
 
+def test_input_stats_ragged(ctx):
+    """Several z chunks with a short last one, a partial x block and a thin y extent: the
+    neighbour loads fetched one plane ahead stop at the chunk's end and wrap periodically."""
+    say("[gpu] input statistics on a ragged grid")
+    rho, u = synth.random_fields((37, 7, 150), seed=11)
+    st = ctx.input_stats(dev(rho), dev(u), 0.07)
+    o = F.input_stats(rho, u, 0.07)
+    for k in ("mean_rho", "ek", "enstrophy"):
+        assert abs(st[k] - o[k]) <= 1e-10 * abs(o[k]), k
+    assert st["n_nonfinite"] == 0
+
+
+@pytest.mark.parametrize("n", [1, 4099, 20_000_003])
+def test_reduce_check_sizes(ctx, n):
+    """The two-pass FP64 reduction over one record, a few records and more records than
+    the first pass has workgroups, against host FP64 sums; repeated calls agree bit for bit."""
+    say(f"[gpu] FP64 reduction of {n} values")
+    rng = np.random.default_rng(n)
+    ha = rng.standard_normal(n).astype(np.float32)
+    hb = rng.standard_normal(n).astype(np.float32)
+    a, b = dev(ha), dev(hb)
+    s1 = ctx.reduce_check(a, b)
+    s2 = ctx.reduce_check(a, b)
+    assert list(s1) == list(s2)
+    da, db = ha.astype(np.float64), hb.astype(np.float64)
+    assert abs(s1[0] - da.sum()) <= 1e-10 * np.abs(da).sum()
+    assert abs(s1[1] - (da * da).sum()) <= 1e-10 * (da * da).sum()
+    assert abs(s1[2] - (da * db).sum()) <= 1e-10 * np.abs(da * db).sum()
+
+
 def test_grad_closure_standalone(ctx):
     say("[gpu] standalone gradient/closure pass")
     rho, u = synth.random_fields((18, 20, 22), seed=6)
