@@ -106,6 +106,8 @@ CASES = [
     ("ragged_box8", (21, 30, 37), F.BOX, 8),
     ("ragged_box10_tall", (37, 61, 35), F.BOX, 10),
     ("ragged_box16_tall", (41, 57, 34), F.BOX, 16),
+    ("support_box16_tall", (17, 17, 17), F.BOX, 16),  # window as wide as the grid
+    ("support_box10_tall", (11, 30, 11), F.BOX, 10),
     ("gauss4_40", (40, 36, 33), F.GAUSS, 4),
 ]
 
