@@ -29,15 +29,22 @@ constexpr float kGeluA = 0.044715f;
 
 __device__ __forceinline__ __bf16 to_bf16(float f) { return static_cast<__bf16>(f); }
 
-// x * sigmoid(u), u = 2 c (x + a x^3): the tanh form 0.5 x (1 + tanh(c (x + a x^3))).
+// exp(-u) for u = 2 c (x + a x^3) as 2^(x (k0 + k1 x^2)), k0 = -2 c log2(e), k1 = a k0:
+// one multiply less than forming u first
+constexpr float kGeluK0 = (float)(-2.0 * 0.7978845608028654 * 1.4426950408889634);
+constexpr float kGeluK1 = (float)(-2.0 * 0.7978845608028654 * 1.4426950408889634 * 0.044715);
+
+__device__ __forceinline__ float gelu_exp(float x) {
+  return __builtin_amdgcn_exp2f(x * fmaf(kGeluK1, x * x, kGeluK0));
+}
+
+// x * sigmoid(u): the tanh form 0.5 x (1 + tanh(c (x + a x^3))).
 __device__ __forceinline__ float gelu(float x) {
-  const float u = 2.f * kGeluC * x * fmaf(kGeluA, x * x, 1.f);
-  return x * __builtin_amdgcn_rcpf(1.f + __expf(-u));
+  return x * __builtin_amdgcn_rcpf(1.f + gelu_exp(x));
 }
 
 __device__ __forceinline__ float gelu_grad(float x) {
-  const float u = 2.f * kGeluC * x * fmaf(kGeluA, x * x, 1.f);
-  const float s = __builtin_amdgcn_rcpf(1.f + __expf(-u));
+  const float s = __builtin_amdgcn_rcpf(1.f + gelu_exp(x));
   const float du = 2.f * kGeluC * fmaf(3.f * kGeluA, x * x, 1.f);
   return fmaf(x * s * (1.f - s), du, s);
 }
