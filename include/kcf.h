@@ -344,7 +344,8 @@ int kcf_mlp_predict(kcf_mlp *mlp, const float *x, int64_t n, float *y_std);
  * filter width delta. Points whose standardised inputs leave the envelope, or are not finite,
  * take the gradient model rho_bar * m2 * G G^T instead. mask (device, ceil(N/16) uint16
  * words, bit p of word t = point 16 t + p, may be NULL) marks those points; n_fallback (host,
- * may be NULL; then the call synchronises) counts them. */
+ * may be NULL) counts them: when it is given the call synchronises the stream, with NULL the
+ * call is asynchronous. */
 int kcf_mlp_infer_field(kcf_mlp *mlp, const kcf_grid *grid, const float *rho_bar,
                         const float *ut, double delta, double m2, float *tau, uint16_t *mask,
                         int64_t *n_fallback);

@@ -191,6 +191,8 @@ def _ptr(t, dtype=None):
     if t is None:
         return None
     import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("expected a torch tensor")
     if not t.is_cuda:
         raise ValueError("expected a device tensor")
     if not t.is_contiguous():
@@ -198,6 +200,29 @@ def _ptr(t, dtype=None):
     if t.dtype != (dtype or torch.float32):
         raise ValueError(f"expected {dtype or torch.float32}, got {t.dtype}")
     return C.c_void_p(t.data_ptr())
+
+
+def _need(*specs):
+    """Checks (tensor, numel, name) triples: each tensor that is given must hold exactly numel
+    elements. Every wrapper runs this on all its tensors before it takes a pointer or calls
+    the library, so a mismatched buffer never reaches a kernel."""
+    for t, numel, name in specs:
+        if t is not None and t.numel() != numel:
+            raise ValueError(f"{name}: expected {numel} elements, got {t.numel()} (shape "
+                             f"{tuple(t.shape)})")
+
+
+def _sized(t, numel, name, dtype=None):
+    """Device pointer of t after its size check (None stays None)."""
+    _need((t, numel, name))
+    return _ptr(t, dtype)
+
+
+def _grid3(t, name="rho"):
+    """(nz, ny, nx) of a scalar field given as (nz, ny, nx) or (1, nz, ny, nx)."""
+    if t is None or t.dim() not in (3, 4) or (t.dim() == 4 and t.shape[0] != 1):
+        raise ValueError(f"{name}: expected a (nz, ny, nx) field")
+    return tuple(int(v) for v in t.shape[-3:])
 
 
 def params(c_s=0.11, c_nu=0.02, theta=1.0, nu_mol=0.0, dt=0.0, gm_form=0, m2_mode=0,
@@ -217,11 +242,25 @@ def alloc_outputs(shape, device, fields=("rho_bar", "ut", "tau", "grad", "tau_gm
             for f in fields}
 
 
-def _outputs_struct(d):
+def _outputs_need(d, n):
+    """Size checks of an output dict name -> tensor on a grid of n points."""
+    if d:
+        bad = set(d) - set(OUT_SIZES)
+        if bad:
+            raise ValueError(f"unknown output fields {sorted(bad)}")
+        _need(*[(t, OUT_SIZES[k] * n, k) for k, t in d.items()])
+
+
+def _outputs_struct(d, n=None):
+    """Outputs struct of a dict name -> tensor; with n (points of the grid) every tensor must
+    hold OUT_SIZES[name] * n elements."""
+    if n is not None:
+        _outputs_need(d, n)
     o = Outputs()
     for name in OUT_SIZES:
         t = d.get(name) if d else None
-        setattr(o, name, _ptr(t).value if t is not None else None)
+        p = _ptr(t)
+        setattr(o, name, p.value if p is not None else None)
     return o
 
 
@@ -275,22 +314,34 @@ class Context:
     def filter_favre(self, rho, u, h, filters, outs, cp=None, stats=True):
         """rho (nz,ny,nx), u (3,nz,ny,nx) device float32; filters: list of (kind, n[, precision]);
         outs: list (one per filter) of dicts name -> tensor. Returns list of stats dicts."""
-        nz, ny, nx = rho.shape
+        nz, ny, nx = _grid3(rho)
+        n = nx * ny * nz
         g = Grid(nx, ny, nz, h)
         nf = len(filters)
+        if not 1 <= nf <= 4:
+            raise ValueError(f"1 to 4 filters per call, got {nf}")
+        if len(outs) != nf:
+            raise ValueError(f"{nf} filters but {len(outs)} output sets")
+        _need((rho, n, "rho"), (u, 3 * n, "u"))
+        for o in outs:
+            _outputs_need(o, n)
         fa = (Filter * nf)(*[Filter(*f) if len(f) == 3 else Filter(f[0], f[1], 0) for f in filters])
-        oa = (Outputs * nf)(*[_outputs_struct(o) for o in outs])
+        oa = (Outputs * nf)(*[_outputs_struct(o, n) for o in outs])
+        pr, pu = _sized(rho, n, "rho"), _sized(u, 3 * n, "u")
         st = (WidthStats * nf)() if stats else None
-        check(self._lib.kcf_filter_favre(self.handle, C.byref(g), fa, nf, _ptr(rho), _ptr(u), oa,
+        check(self._lib.kcf_filter_favre(self.handle, C.byref(g), fa, nf, pr, pu, oa,
                                          C.byref(cp) if cp is not None else None, st))
         return [s.as_dict() for s in st] if stats else None
 
     def grad_closure(self, rho_bar, ut, tau, h, delta, m2, outs, cp=None, stats=True):
-        nz, ny, nx = rho_bar.shape[-3:]
+        nz, ny, nx = _grid3(rho_bar, "rho_bar")
+        n = nx * ny * nz
         g = Grid(nx, ny, nz, h)
-        o = _outputs_struct(outs)
+        _need((rho_bar, n, "rho_bar"), (ut, 3 * n, "ut"), (tau, 6 * n, "tau"))
+        o = _outputs_struct(outs, n)
+        pr, pu, pt = _sized(rho_bar, n, "rho_bar"), _sized(ut, 3 * n, "ut"), _sized(tau, 6 * n, "tau")
         st = WidthStats() if stats else None
-        check(self._lib.kcf_grad_closure(self.handle, C.byref(g), _ptr(rho_bar), _ptr(ut), _ptr(tau),
+        check(self._lib.kcf_grad_closure(self.handle, C.byref(g), pr, pu, pt,
                                          delta, m2, C.byref(cp) if cp is not None else None,
                                          C.byref(o), C.byref(st) if stats else None))
         return st.as_dict() if stats else None
@@ -298,24 +349,32 @@ class Context:
     def sgs_carrier(self, rho, u, h, filt, f_sgs=None, f_h2=None, stats=True):
         """D3Q27 SGS carrier of one filter (kind, n[, precision]): f_sgs and f_h2 are optional
         (27, nz, ny, nx) device float32 tensors; returns the statistics dict or None."""
-        nz, ny, nx = rho.shape
+        nz, ny, nx = _grid3(rho)
+        n = nx * ny * nz
         g = Grid(nx, ny, nz, h)
         fl = Filter(*filt) if len(filt) == 3 else Filter(filt[0], filt[1], 0)
+        _need((rho, n, "rho"), (u, 3 * n, "u"), (f_sgs, 27 * n, "f_sgs"), (f_h2, 27 * n, "f_h2"))
+        ptrs = (_sized(rho, n, "rho"), _sized(u, 3 * n, "u"), _sized(f_sgs, 27 * n, "f_sgs"),
+                _sized(f_h2, 27 * n, "f_h2"))
         st = CarrierStats() if stats else None
-        check(self._lib.kcf_sgs_carrier(self.handle, C.byref(g), C.byref(fl), _ptr(rho), _ptr(u),
-                                        _ptr(f_sgs), _ptr(f_h2), C.byref(st) if stats else None))
+        check(self._lib.kcf_sgs_carrier(self.handle, C.byref(g), C.byref(fl), *ptrs,
+                                        C.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
     def sgs_moment3(self, rho, u, h, filt, theta=None, m3=None, theta_t=None, stats=True):
         """Third-order SGS moment of one filter (kind, n[, precision]): m3 is an optional
         (10, nz, ny, nx) device float32 tensor, theta_t an optional (nz, ny, nx) one (needs
         theta); returns the statistics dict or None."""
-        nz, ny, nx = rho.shape
+        nz, ny, nx = _grid3(rho)
+        n = nx * ny * nz
         g = Grid(nx, ny, nz, h)
         fl = Filter(*filt) if len(filt) == 3 else Filter(filt[0], filt[1], 0)
+        _need((rho, n, "rho"), (u, 3 * n, "u"), (theta, n, "theta"), (m3, 10 * n, "m3"),
+              (theta_t, n, "theta_t"))
+        ptrs = (_sized(rho, n, "rho"), _sized(u, 3 * n, "u"), _sized(theta, n, "theta"),
+                _sized(m3, 10 * n, "m3"), _sized(theta_t, n, "theta_t"))
         st = Moment3Stats() if stats else None
-        check(self._lib.kcf_sgs_moment3(self.handle, C.byref(g), C.byref(fl), _ptr(rho), _ptr(u),
-                                        _ptr(theta), _ptr(m3), _ptr(theta_t),
+        check(self._lib.kcf_sgs_moment3(self.handle, C.byref(g), C.byref(fl), *ptrs,
                                         C.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
@@ -324,31 +383,50 @@ class Context:
         """A priori KC-MP SGS moment and relaxation-rate field of one filter (kind, n[,
         precision]); outputs are optional device float32 tensors ((6, nz, ny, nx) for m_sgs and m_ce,
         (nz, ny, nx) for the rates). Returns the statistics dict or None."""
-        nz, ny, nx = rho.shape
+        nz, ny, nx = _grid3(rho)
+        n = nx * ny * nz
         g = Grid(nx, ny, nz, h)
         fl = Filter(*filt) if len(filt) == 3 else Filter(filt[0], filt[1], 0)
         kp = KcParams(nu, dt, theta, c_nu, rho_ref_one)
+        _need((rho, n, "rho"), (u, 3 * n, "u"), (m_sgs, 6 * n, "m_sgs"), (m_ce, 6 * n, "m_ce"),
+              (k_sgs, n, "k_sgs"), (nu_t_eff, n, "nu_t_eff"), (omega_sgs, n, "omega_sgs"))
+        pr, pu = _sized(rho, n, "rho"), _sized(u, 3 * n, "u")
+        outs = (_sized(m_sgs, 6 * n, "m_sgs"), _sized(m_ce, 6 * n, "m_ce"),
+                _sized(k_sgs, n, "k_sgs"), _sized(nu_t_eff, n, "nu_t_eff"),
+                _sized(omega_sgs, n, "omega_sgs"))
         st = KcStats() if stats else None
-        check(self._lib.kcf_kc_mp(self.handle, C.byref(g), C.byref(fl), _ptr(rho), _ptr(u),
-                                  C.byref(kp), _ptr(m_sgs), _ptr(m_ce), _ptr(k_sgs), _ptr(nu_t_eff),
-                                  _ptr(omega_sgs), C.byref(st) if stats else None))
+        check(self._lib.kcf_kc_mp(self.handle, C.byref(g), C.byref(fl), pr, pu, C.byref(kp), *outs,
+                                  C.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
     def input_stats(self, rho, u, h):
-        nz, ny, nx = rho.shape
+        nz, ny, nx = _grid3(rho)
+        n = nx * ny * nz
         g = Grid(nx, ny, nz, h)
+        _need((rho, n, "rho"), (u, 3 * n, "u"))
+        pr, pu = _sized(rho, n, "rho"), _sized(u, 3 * n, "u")
         s = InputSummary()
-        check(self._lib.kcf_input_stats(self.handle, C.byref(g), _ptr(rho), _ptr(u), C.byref(s)))
+        check(self._lib.kcf_input_stats(self.handle, C.byref(g), pr, pu, C.byref(s)))
         return dict(mean_rho=s.mean_rho, ek=s.ek, enstrophy=s.enstrophy, n_nonfinite=s.n_nonfinite)
 
     def reduce_check(self, a, b=None):
         out = (C.c_double * 3)()
-        check(self._lib.kcf_reduce_check(self.handle, _ptr(a), _ptr(b), a.numel(), out))
+        _need((b, a.numel(), "b"))
+        pa, pb = _ptr(a), _ptr(b)
+        check(self._lib.kcf_reduce_check(self.handle, pa, pb, a.numel(), out))
         return list(out)
 
 
 N_PARAMS = 9670
 N_NORM = 68
+
+
+def _rows(x, ncol, name):
+    """Row count of an (n, ncol) matrix, checked."""
+    if x is None or x.dim() != 2 or x.shape[1] != ncol or x.shape[0] < 1:
+        raise ValueError(f"{name}: expected an (n, {ncol}) matrix, got "
+                         f"{None if x is None else tuple(x.shape)}")
+    return int(x.shape[0])
 
 
 def _f32(a, n):
@@ -408,37 +486,59 @@ class MLP:
         return s.value
 
     def fit_norm(self, x, y):
-        check(self._lib.kcf_mlp_fit_norm(self.handle, _ptr(x), _ptr(y), x.shape[0]))
+        n = _rows(x, 14, "x")
+        _need((y, 6 * n, "y"))
+        px, py = _ptr(x), _ptr(y)
+        check(self._lib.kcf_mlp_fit_norm(self.handle, px, py, n))
+
+    def _batch(self, x, y, idx, batch):
+        import torch
+        n = _rows(x, 14, "x")
+        _need((y, 6 * n, "y"))
+        if batch <= 0 or (idx is None and batch > n):
+            raise ValueError(f"batch {batch} outside 1..{n}")
+        if idx is not None and idx.numel() < batch:
+            raise ValueError(f"idx: {idx.numel()} indices for a batch of {batch}")
+        return n, _ptr(y), _ptr(idx, torch.int32)
 
     def train_step(self, x, y, idx, batch, lr, loss_out=None):
-        import torch
-        check(self._lib.kcf_mlp_train_step(self.handle, _ptr(x), _ptr(y), x.shape[0],
-                                           _ptr(idx, torch.int32), batch, lr, _ptr(loss_out)))
+        _need((loss_out, 1, "loss_out"))
+        n, py, pi = self._batch(x, y, idx, batch)
+        px, pl = _ptr(x), _ptr(loss_out)
+        check(self._lib.kcf_mlp_train_step(self.handle, px, py, n, pi, batch, lr, pl))
 
     def grads(self, x, y, idx, batch):
         import numpy as np
-        import torch
+        n, py, pi = self._batch(x, y, idx, batch)
+        px = _ptr(x)
         g = np.empty(N_PARAMS, dtype=np.float32)
         loss = C.c_double()
-        check(self._lib.kcf_mlp_grads(self.handle, _ptr(x), _ptr(y), x.shape[0], _ptr(idx, torch.int32),
+        check(self._lib.kcf_mlp_grads(self.handle, px, py, n, pi,
                                       batch, g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)))
         return loss.value, g
 
     def predict(self, x):
         import torch
-        y = torch.empty((x.shape[0], 6), dtype=torch.float32, device=x.device)
-        check(self._lib.kcf_mlp_predict(self.handle, _ptr(x), x.shape[0], _ptr(y)))
+        n = _rows(x, 14, "x")
+        px = _ptr(x)
+        y = torch.empty((n, 6), dtype=torch.float32, device=x.device)
+        check(self._lib.kcf_mlp_predict(self.handle, px, n, _ptr(y)))
         return y
 
     def infer_field(self, rho_bar, ut, h, delta, m2, tau_out=None, mask_out=None, count=True):
         import torch
-        nz, ny, nx = rho_bar.shape[-3:]
+        nz, ny, nx = _grid3(rho_bar, "rho_bar")
+        n = nx * ny * nz
         g = Grid(nx, ny, nz, h)
+        _need((rho_bar, n, "rho_bar"), (ut, 3 * n, "ut"), (tau_out, 6 * n, "tau_out"),
+              (mask_out, (n + 15) // 16, "mask_out"))
         if tau_out is None:
             tau_out = torch.empty((6, nz, ny, nx), dtype=torch.float32, device=rho_bar.device)
+        ptrs = (_sized(rho_bar, n, "rho_bar"), _sized(ut, 3 * n, "ut"))
+        pt = _sized(tau_out, 6 * n, "tau_out")
+        pm = _sized(mask_out, (n + 15) // 16, "mask_out", torch.int16)
         nfb = C.c_int64()
-        check(self._lib.kcf_mlp_infer_field(self.handle, C.byref(g), _ptr(rho_bar), _ptr(ut), delta, m2,
-                                            _ptr(tau_out), _ptr(mask_out, torch.int16),
+        check(self._lib.kcf_mlp_infer_field(self.handle, C.byref(g), *ptrs, delta, m2, pt, pm,
                                             C.byref(nfb) if count else None))
         return tau_out, (nfb.value if count else None)
 
@@ -452,17 +552,23 @@ class MLP:
 def mlp_features(ctx, rho_bar, ut, tau, h, delta, with_targets=True):
     """Network inputs (N, 14) and targets (N, 6) of every grid point (device tensors)."""
     import torch
-    nz, ny, nx = rho_bar.shape[-3:]
+    nz, ny, nx = _grid3(rho_bar, "rho_bar")
     n = nx * ny * nz
     g = Grid(nx, ny, nz, h)
+    _need((rho_bar, n, "rho_bar"), (ut, 3 * n, "ut"), (tau, 6 * n, "tau"))
+    pr, pu = _sized(rho_bar, n, "rho_bar"), _sized(ut, 3 * n, "ut")
+    pt = _sized(tau, 6 * n, "tau") if with_targets else None
+    if with_targets and pt is None:
+        raise ValueError("targets need tau")
     x = torch.empty((n, 14), dtype=torch.float32, device=rho_bar.device)
     y = torch.empty((n, 6), dtype=torch.float32, device=rho_bar.device) if with_targets else None
-    check(ctx._lib.kcf_mlp_features(ctx.handle, C.byref(g), _ptr(rho_bar), _ptr(ut),
-                                    _ptr(tau) if with_targets else None, delta, _ptr(x), _ptr(y)))
+    check(ctx._lib.kcf_mlp_features(ctx.handle, C.byref(g), pr, pu, pt, delta, _ptr(x), _ptr(y)))
     return x, y
 
 
 def column_stats(ctx, X):
+    if X.dim() != 2 or not 1 <= X.shape[1] <= 32:
+        raise ValueError(f"X: expected an (n, ncol <= 32) matrix, got {tuple(X.shape)}")
     ncol = X.shape[1]
     arrs = [(C.c_double * ncol)() for _ in range(4)]
     check(ctx._lib.kcf_mlp_column_stats(ctx.handle, _ptr(X), X.shape[0], ncol, *arrs))

@@ -138,3 +138,21 @@ def test_pointwise_carrier_equals_field_carrier():
     for n, (k, j, i) in enumerate(pts):
         assert np.max(np.abs(fs[n] - r["f_sgs"][:, k, j, i])) < 1e-15
         assert np.max(np.abs(fh[n] - r["f_h2"][:, k, j, i])) < 1e-15
+
+
+def test_carrier_stats_on_literal_populations():
+    """carrier_stats on hand-built populations: <sum_i f_i^2> is a mean over points of the
+    sum over the 27 populations (two points with 27 values 1 and 27 values 3 give
+    (27 + 243) / 2 = 135); err_l2 = 0 when f_h2 = f_sgs, rel_err = 1 when f_h2 = 0,
+    rel_err = 1/2 when f_h2 = f_sgs / 2, and err_l2 = 27 * (1^2 + 2^2) / 2 for f_h2 = 0 and 1
+    on the two points."""
+    f = np.empty((27, 2))
+    f[:, 0], f[:, 1] = 1.0, 3.0
+    st = K.carrier_stats(f, f.copy())
+    assert st["sgs_l2"] == 135.0 and st["err_l2"] == 0.0 and st["rel_err"] == 0.0
+    assert K.carrier_stats(f, np.zeros_like(f))["rel_err"] == 1.0
+    assert abs(K.carrier_stats(f, 0.5 * f)["rel_err"] - 0.5) < 1e-15
+    fh = np.empty_like(f)
+    fh[:, 0], fh[:, 1] = 0.0, 1.0
+    assert K.carrier_stats(f, fh)["err_l2"] == 27 * (1.0 + 4.0) / 2
+    assert K.carrier_stats(np.zeros_like(f), np.zeros_like(f))["rel_err"] == 0.0

@@ -339,3 +339,23 @@ def test_q_criterion_cases():
     rng = np.random.default_rng(3)
     Gr = rng.standard_normal((3, 3, 5))
     assert np.allclose(F.q_criterion(Gr), -0.5 * np.einsum("ij...,ji...->...", Gr, Gr), atol=1e-14)
+
+
+def test_resolved_energy_single_mode_closed_form():
+    """rho = c (constant), u_i = a_i cos(k.x): rho_bar = c and ut_i = a_i G3(k) cos(k.x), so
+    <rho_bar |ut|^2 / 2> = c G3(k)^2 |a|^2 / 4 (the mean of cos^2 over whole periods is 1/2).
+    A dropped 1/2, a dropped rho_bar or the unfiltered velocity all fail this."""
+    n = 16
+    h = 2 * np.pi / n
+    X, Y, Z = synth.grid_coords(n)
+    kv = np.array([2, 1, 3])
+    a = np.array([0.3, -0.2, 0.1])
+    phi = kv[0] * X + kv[1] * Y + kv[2] * Z
+    u = np.stack([a[i] * np.cos(phi) for i in range(3)])
+    c = 2.0
+    rho = np.full((n, n, n), c)
+    for kind, nd in ((F.BOX, 4), (F.GAUSS, 2)):
+        g3 = np.prod([F.transfer(kind, nd, kk * h) for kk in kv])
+        st = F.full_path(rho, u, kind, nd, h)["stats"]
+        assert abs(st["ke_resolved"] - c * g3 ** 2 * np.dot(a, a) / 4) < 1e-15
+        assert abs(st["mean_rho_bar"] - c) < 1e-14

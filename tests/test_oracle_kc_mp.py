@@ -93,3 +93,35 @@ def test_pointwise_equals_field():
         assert np.max(np.abs(m[n] - r["m_sgs"][:, :, a, b, c])) < 1e-14
         assert abs(k[n] - r["k_sgs"][a, b, c]) < 1e-14
         assert abs(om[n] - r["omega_sgs"][a, b, c]) < 1e-10 * abs(om[n])
+
+
+def test_kc_mp_stats_on_literal_arrays():
+    """kc_mp_stats on hand-built arrays: the relative error runs over all nine pairs (a
+    symmetric perturbation d of the xy pair counts twice), Pearson r is +1 for an affine
+    image and -1 for a negated one, the clipped fractions count nu_t_eff <= nu (equality
+    included) and the means are plain means."""
+    rng = np.random.default_rng(5)
+    t = rng.standard_normal((3, 3, 50))
+    t = 0.5 * (t + np.swapaxes(t, 0, 1))
+    d = 0.1
+    m = t.copy()
+    m[0, 1] += d
+    m[1, 0] += d
+    nu = 1e-3
+    nue = np.full(50, 2e-3)
+    nue[:10] = nu  # ten points exactly at the molecular viscosity: clipped
+    nue_ex = np.full(50, 2e-3)
+    nue_ex[:4] = 0.5 * nu
+    r = dict(m_sgs=m, tau=t, k_sgs=np.arange(50.0), k_exact=np.full(50, 2.0),
+             omega_sgs=np.full(50, 1.5), omega_exact=np.linspace(1.0, 2.0, 50),
+             nu_t_eff=nue, nu_t_exact=nue_ex)
+    st = KC.kc_mp_stats(r, nu)
+    assert abs(st["rel_err"] - np.sqrt(2 * 50 * d * d / np.sum(t ** 2))) < 1e-15
+    assert st["clip"] == 10 / 50 and st["clip_exact"] == 4 / 50
+    assert st["mean_k"] == 24.5 and st["mean_k_exact"] == 2.0
+    assert st["mean_omega"] == 1.5 and abs(st["mean_omega_exact"] - 1.5) < 1e-15
+    r2 = dict(r, m_sgs=3.0 * t + 1.0)
+    assert all(abs(c - 1) < 1e-14 for c in KC.kc_mp_stats(r2, nu)["corr"])
+    r3 = dict(r, m_sgs=-t)
+    assert all(abs(c + 1) < 1e-14 for c in KC.kc_mp_stats(r3, nu)["corr"])
+    assert KC.kc_mp_stats(dict(r, m_sgs=t), nu)["rel_err"] == 0.0

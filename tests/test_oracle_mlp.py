@@ -150,3 +150,12 @@ def test_infer_fallback():
     assert np.array_equal(tau[3], tau_gm[3]) and np.array_equal(tau[7], tau_gm[7])
     y, _ = M.forward(p, feats[:1])
     assert np.allclose(tau[0], rho[0] * y[0])
+
+
+def test_norm_stats_population_std():
+    """Column means and POPULATION standard deviations: the column 1, 2, 3, 4 has mean 5/2
+    and std sqrt(5/4) (the sample std would be sqrt(5/3)); a constant column has std 0."""
+    X = np.array([[1.0, 7.0], [2.0, 7.0], [3.0, 7.0], [4.0, 7.0]])
+    mu, sd = M.norm_stats(X)
+    assert mu[0] == 2.5 and mu[1] == 7.0
+    assert abs(sd[0] - math.sqrt(1.25)) < 1e-15 and sd[1] == 0.0
