@@ -6,6 +6,7 @@ on the same float32 inputs. Statistics: GPU FP64 reductions of the GPU's own fie
 with host FP64 sums of those fields to 1e-10 relative; against the oracle's statistics
 they agree to the field tolerance.
 """
+import ctypes as C
 import math
 import sys
 import zlib
@@ -354,9 +355,13 @@ def test_error_paths(ctx):
     with pytest.raises(kcf.KcfError) as e:
         ctx.filter_favre(r, u, 0.1, [(F.GAUSS, 10)], o)  # R = 15 > 12
     assert e.value.code == kcf.EUNSUPPORTED
-    with pytest.raises(kcf.KcfError) as e:
+    with pytest.raises(ValueError):  # the binding rejects it before the library
         ctx.filter_favre(r, u, 0.1, [], [])
-    assert e.value.code == kcf.EINVAL
+    g = kcf.Grid(8, 8, 8, 0.1)  # and so does the library
+    assert ctx._lib.kcf_filter_favre(ctx.handle, C.byref(g), (kcf.Filter * 1)(), 0, kcf._ptr(r),
+                                     kcf._ptr(u), (kcf.Outputs * 1)(), None, None) == kcf.EINVAL
+    with pytest.raises(ValueError):  # outputs sized for another grid
+        ctx.filter_favre(r, u, 0.1, [(F.BOX, 2)], [kcf.alloc_outputs((8, 8, 9), "cuda")])
     with pytest.raises(kcf.KcfError) as e:
         ctx.filter_favre(r, u, -0.1, [(F.BOX, 2)], o)
     assert e.value.code == kcf.EINVAL
