@@ -214,6 +214,24 @@ int kcf_filter_favre(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filte
                      int n_filters, const float *rho, const float *u, const kcf_outputs *outs,
                      const kcf_closure_params *cp, kcf_width_stats *stats);
 
+/* The box path of kcf_filter_favre for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * results, with no context. Work is enqueued on `stream` (hipStream_t, NULL = default stream)
+ * of HIP device `device`. The call allocates nothing: its FP64 statistics records, reduction
+ * totals and sums live in a 16 MiB device array of the library that each GPU holds for the life
+ * of the process. Every call on a GPU shares that array, so calls that overlap on one GPU (on
+ * different streams or host threads) race and must be serialised by the caller. Without stats
+ * the array is not used and the call is asynchronous; with stats it synchronises the stream.
+ * Limits: box filters only (widths up to 16h in FP32, 8h in FP64); with stats, at most
+ * 52 168 statistics records per width (one per wave of the box kernel: a 512^3 grid needs at
+ * most 27 520; 1024^3 grids exceed it at the narrow widths).
+ * Errors: as kcf_filter_favre; KCF_EUNSUPPORTED for a Gaussian or wider box filter and for a
+ * grid whose records exceed the array, KCF_EINVAL for a bad device index. */
+int kcf_filter_favre_noalloc(const kcf_grid *grid, const kcf_filter *filters, int n_filters,
+                             const float *rho, const float *u, const kcf_outputs *outs,
+                             const kcf_closure_params *cp, kcf_width_stats *stats, int device,
+                             void *stream);
+
 /* Gradient, closures and statistics from stored filtered fields rho_bar (N), ut (3N) and
  * tau (6N, may be NULL: then k_sgs/nu_t/omega_t and tau statistics are not available and
  * must not be requested). delta = filter width, m2 = kernel second moment. */

@@ -1,6 +1,7 @@
 // C-ABI layer of libkcf: argument checks, filter taps, launch geometry, FP64 statistics.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -311,6 +312,65 @@ int run_monomials(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, in
   return KCF_OK;
 }
 
+// Taps, radius and precision of each width of a filter_favre call, after the argument checks
+// both filter_favre entry points share.
+struct WidthPlan {
+  Taps taps[4];
+  int radii[4];
+  int fp64[4];
+  int use_box[4];  // the sliding-sum box kernel applies
+};
+
+int plan_widths(const kcf_grid* grid, const kcf_filter* filters, int nf,
+                const kcf_closure_params* cp, WidthPlan& P) {
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!filters) return fail(KCF_EINVAL, "NULL argument");
+  if (nf < 1 || nf > 4) return fail(KCF_EINVAL, "n_filters must be 1..4");
+  if ((rc = check_closure(cp))) return rc;
+  for (int f = 0; f < nf; ++f) {
+    if ((rc = compute_taps(filters[f].kind, filters[f].delta_over_h, grid->h, P.taps[f]))) return rc;
+    P.radii[f] = P.taps[f].R;
+    if (P.taps[f].R > kMaxR) return fail(KCF_EUNSUPPORTED, "filter radius above 12 cells");
+    const int nmin = std::min(grid->nx, std::min(grid->ny, grid->nz));
+    if (2 * P.taps[f].R + 1 > nmin)
+      return fail(KCF_EUNSUPPORTED, "filter support 2R+1 exceeds the grid");
+    const int p = filters[f].precision;
+    if (p < 0 || p > 2) return fail(KCF_EINVAL, "precision must be 0 (auto), 1 (fp32) or 2 (fp64)");
+    P.fp64[f] = p == 2 || (p == 0 && filters[f].delta_over_h <= 4);
+    P.use_box[f] = filters[f].kind == KCF_BOX && box_supported(P.radii[f], P.fp64[f]);
+  }
+  if (grid->ny > 65535) return fail(KCF_EUNSUPPORTED, "ny above 65535");
+  return KCF_OK;
+}
+
+// Launch geometry of the box kernel of one width.
+void box_args_for(FilterArgs& A, const kcf_grid* grid, const float* rho, const float* u, int R,
+                  int fp64) {
+  const BoxGeom bg = box_geometry(R, fp64);
+  std::memset(&A, 0, sizeof(A));
+  A.rho = rho;
+  A.u = u;
+  A.nx = grid->nx;
+  A.ny = grid->ny;
+  A.nz = grid->nz;
+  A.ntot = (int64_t)grid->nx * grid->ny * grid->nz;
+  A.inv2h = (float)(1.0 / (2.0 * grid->h));
+  A.ntx = (grid->nx + bg.tile_x - 1) / bg.tile_x;
+  A.nty = (grid->ny + bg.tile_y - 1) / bg.tile_y;
+  A.ntiles = A.ntx * A.nty;
+  A.nzc = choose_zchunks(A.ntiles, grid->nz, R, bg.blocks_per_cu);
+  A.zlen = (grid->nz + A.nzc - 1) / A.nzc;
+  A.nzc = (grid->nz + A.zlen - 1) / A.zlen;
+  A.tiles_per_xcd = (A.ntiles * A.nzc + 7) / 8;
+  A.strip_w = bg.strip_w;
+}
+
+// FP64 statistics records the box kernel of a width writes (one per wave).
+int64_t box_records(const FilterArgs& A, int R, int fp64) {
+  return (int64_t)A.ntiles * A.nzc * box_geometry(R, fp64).stat_waves;
+}
+
 }  // namespace
 
 namespace kcf {
@@ -318,6 +378,38 @@ int api_fail(int code, const char* msg) { return fail(code, msg); }
 hipStream_t ctx_stream(kcf_ctx* c) { return c->stream; }
 int ctx_device(kcf_ctx* c) { return c->device; }
 }  // namespace kcf
+
+// ---- scratch of the no-allocation entry point
+// Device memory of kcf_filter_favre_noalloc: the reduced sums of up to four widths, the chunk
+// totals of the two-pass reduction and the per-wave FP64 records of one width (the widths are
+// reduced one after the other, so they reuse the record area). Each GPU the library runs on
+// holds its own copy for the life of the process.
+constexpr size_t kNoAllocSums = 4 * kNStat;
+constexpr size_t kNoAllocRed = (size_t)kRedBlocks * kNStat;
+constexpr size_t kNoAllocDoubles = (size_t)2 << 20;  // 16 MiB
+constexpr size_t kNoAllocRecords = (kNoAllocDoubles - kNoAllocSums - kNoAllocRed) / kNStat;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (current when called), looked up once per device.
+// Host code must use this address: the name itself is a host-side stand-in.
+int scratch_address(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return fail(KCF_EUNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return KCF_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -417,52 +509,20 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
                      const float* rho, const float* u, const kcf_outputs* outs,
                      const kcf_closure_params* cp, kcf_width_stats* stats) {
   if (!c) return fail(KCF_EINVAL, "ctx is NULL");
-  int rc = check_grid(grid);
+  WidthPlan P;
+  int rc = plan_widths(grid, filters, nf, cp, P);
   if (rc) return rc;
-  if (!filters || !outs || !rho || !u) return fail(KCF_EINVAL, "NULL argument");
-  if (nf < 1 || nf > 4) return fail(KCF_EINVAL, "n_filters must be 1..4");
-  if ((rc = check_closure(cp))) return rc;
-  Taps taps[4];
-  int radii[4], fp64[4];
-  for (int f = 0; f < nf; ++f) {
-    if ((rc = compute_taps(filters[f].kind, filters[f].delta_over_h, grid->h, taps[f]))) return rc;
-    radii[f] = taps[f].R;
-    if (taps[f].R > kMaxR) return fail(KCF_EUNSUPPORTED, "filter radius above 12 cells");
-    const int nmin = std::min(grid->nx, std::min(grid->ny, grid->nz));
-    if (2 * taps[f].R + 1 > nmin)
-      return fail(KCF_EUNSUPPORTED, "filter support 2R+1 exceeds the grid");
-    const int p = filters[f].precision;
-    if (p < 0 || p > 2) return fail(KCF_EINVAL, "precision must be 0 (auto), 1 (fp32) or 2 (fp64)");
-    fp64[f] = p == 2 || (p == 0 && filters[f].delta_over_h <= 4);
-  }
-  if (grid->ny > 65535) return fail(KCF_EUNSUPPORTED, "ny above 65535");
+  if (!outs || !rho || !u) return fail(KCF_EINVAL, "NULL argument");
+  const Taps* taps = P.taps;
+  const int* radii = P.radii;
+  const int* fp64 = P.fp64;
+  const int* use_box = P.use_box;
   KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
   // kernel per width: the sliding-sum box kernel where it applies, the general-tap filter
   // followed by the gradient/closure pass otherwise
-  int use_box[4];
-  for (int f = 0; f < nf; ++f)
-    use_box[f] = filters[f].kind == KCF_BOX && box_supported(radii[f], fp64[f]);
   const int64_t ntot = (int64_t)grid->nx * grid->ny * grid->nz;
   const int64_t plane = (int64_t)grid->nx * grid->ny;
-  auto box_args = [&](FilterArgs& A, int f) {
-    const BoxGeom bg = box_geometry(radii[f], fp64[f]);
-    std::memset(&A, 0, sizeof(A));
-    A.rho = rho;
-    A.u = u;
-    A.nx = grid->nx;
-    A.ny = grid->ny;
-    A.nz = grid->nz;
-    A.ntot = ntot;
-    A.inv2h = (float)(1.0 / (2.0 * grid->h));
-    A.ntx = (grid->nx + bg.tile_x - 1) / bg.tile_x;
-    A.nty = (grid->ny + bg.tile_y - 1) / bg.tile_y;
-    A.ntiles = A.ntx * A.nty;
-    A.nzc = choose_zchunks(A.ntiles, grid->nz, radii[f], bg.blocks_per_cu);
-    A.zlen = (grid->nz + A.nzc - 1) / A.nzc;
-    A.nzc = (grid->nz + A.zlen - 1) / A.zlen;
-    A.tiles_per_xcd = (A.ntiles * A.nzc + 7) / 8;
-    A.strip_w = bg.strip_w;
-  };
+  auto box_args = [&](FilterArgs& A, int f) { box_args_for(A, grid, rho, u, radii[f], fp64[f]); };
   ClosureArgs CG;  // geometry of the gradient/closure pass (same for every width)
   std::memset(&CG, 0, sizeof(CG));
   CG.nx = grid->nx;
@@ -479,7 +539,7 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
       if (use_box[f]) {
         FilterArgs G;
         box_args(G, f);
-        nparts[f] = G.ntiles * G.nzc * box_geometry(radii[f], fp64[f]).stat_waves;
+        nparts[f] = (int)box_records(G, radii[f], fp64[f]);
       } else {
         nparts[f] = (int)grad_closure_records(CG);
       }
@@ -592,6 +652,62 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
     for (int f = 0; f < nf; ++f)
       derive_stats(c->h_sums + f * kNStat, filters[f].delta_over_h * grid->h, taps[f].m2,
+                   &stats[f]);
+  }
+  return KCF_OK;
+}
+
+int kcf_filter_favre_noalloc(const kcf_grid* grid, const kcf_filter* filters, int nf,
+                             const float* rho, const float* u, const kcf_outputs* outs,
+                             const kcf_closure_params* cp, kcf_width_stats* stats, int device,
+                             void* stream) {
+  WidthPlan P;
+  int rc = plan_widths(grid, filters, nf, cp, P);
+  if (rc) return rc;
+  if (!outs || !rho || !u) return fail(KCF_EINVAL, "NULL argument");
+  for (int f = 0; f < nf; ++f)
+    if (!P.use_box[f])
+      return fail(KCF_EUNSUPPORTED, "the no-allocation entry point runs box filters up to 16h "
+                                    "(FP32) or 8h (FP64) only");
+  int ndev = 0;
+  KCF_HIP(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(KCF_EINVAL, "no such device");
+  KCF_HIP(hipSetDevice(device), "hipSetDevice");
+  const hipStream_t st = (hipStream_t)stream;
+  FilterArgs A[4];
+  for (int f = 0; f < nf; ++f) {
+    box_args_for(A[f], grid, rho, u, P.radii[f], P.fp64[f]);
+    if (stats && (size_t)box_records(A[f], P.radii[f], P.fp64[f]) > kNoAllocRecords)
+      return fail(KCF_EUNSUPPORTED,
+                  "grid too large for the statistics scratch of the no-allocation entry point ("
+                  + std::to_string(box_records(A[f], P.radii[f], P.fp64[f])) + " records, " +
+                  std::to_string(kNoAllocRecords) + " available)");
+  }
+  double* scr = nullptr;
+  if (stats && (rc = scratch_address(device, &scr))) return rc;
+  double* d_sums = scr;
+  double* d_red = scr ? scr + kNoAllocSums : nullptr;
+  double* d_part = scr ? scr + kNoAllocSums + kNoAllocRed : nullptr;
+  for (int f = 0; f < nf; ++f) {
+    std::memset(&A[f].wa, 0, sizeof(WidthArgs));
+    set_outputs(A[f].wa, &outs[f]);
+    set_closure(A[f].wa, cp, filters[f].delta_over_h * grid->h, P.taps[f].m2);
+    A[f].wa.partials = d_part;  // every wave writes its record: nothing to clear
+    hipError_t e = launch_box(A[f], P.radii[f], P.fp64[f], 8 * A[f].tiles_per_xcd, st);
+    if (e != hipSuccess) return hip_fail(e, "box filter launch");
+    if (stats) {  // reduce before the next width overwrites the records (same stream)
+      e = launch_reduce(d_part, (int)box_records(A[f], P.radii[f], P.fp64[f]), kNStat,
+                        d_sums + f * kNStat, d_red, st);
+      if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    }
+  }
+  if (stats) {
+    double h_sums[kNoAllocSums];
+    KCF_HIP(hipMemcpyAsync(h_sums, d_sums, sizeof(double) * kNStat * nf, hipMemcpyDeviceToHost,
+                           st), "stats copy");
+    KCF_HIP(hipStreamSynchronize(st), "hipStreamSynchronize");
+    for (int f = 0; f < nf; ++f)
+      derive_stats(h_sums + f * kNStat, filters[f].delta_over_h * grid->h, P.taps[f].m2,
                    &stats[f]);
   }
   return KCF_OK;

@@ -110,6 +110,10 @@ _SIGS = {
     "kcf_filter_favre": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.POINTER(Filter), C.c_int,
                                    C.c_void_p, C.c_void_p, C.POINTER(Outputs),
                                    C.POINTER(ClosureParams), C.POINTER(WidthStats)]),
+    "kcf_filter_favre_noalloc": (C.c_int, [C.POINTER(Grid), C.POINTER(Filter), C.c_int,
+                                           C.c_void_p, C.c_void_p, C.POINTER(Outputs),
+                                           C.POINTER(ClosureParams), C.POINTER(WidthStats),
+                                           C.c_int, C.c_void_p]),
     "kcf_grad_closure": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_double, C.c_double, C.POINTER(ClosureParams),
                                    C.POINTER(Outputs), C.POINTER(WidthStats)]),
@@ -240,6 +244,33 @@ def alloc_outputs(shape, device, fields=("rho_bar", "ut", "tau", "grad", "tau_gm
     nz, ny, nx = shape
     return {f: torch.empty((OUT_SIZES[f], nz, ny, nx), dtype=torch.float32, device=device)
             for f in fields}
+
+
+def filter_favre_noalloc(rho, u, h, filters, outs, cp=None, stats=True, device=0, stream=None):
+    """kcf_filter_favre_noalloc: the box path of Context.filter_favre without a context and
+    without device allocation (see include/kcf.h); same arguments and results."""
+    import torch
+    nz, ny, nx = _grid3(rho)
+    n = nx * ny * nz
+    nf = len(filters)
+    if not 1 <= nf <= 4:
+        raise ValueError(f"1 to 4 filters per call, got {nf}")
+    if len(outs) != nf:
+        raise ValueError(f"{nf} filters but {len(outs)} output sets")
+    _need((rho, n, "rho"), (u, 3 * n, "u"))
+    for o in outs:
+        _outputs_need(o, n)
+    g = Grid(nx, ny, nz, h)
+    fa = (Filter * nf)(*[Filter(*f) if len(f) == 3 else Filter(f[0], f[1], 0) for f in filters])
+    oa = (Outputs * nf)(*[_outputs_struct(o, n) for o in outs])
+    pr, pu = _ptr(rho), _ptr(u)
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    st = (WidthStats * nf)() if stats else None
+    check(lib().kcf_filter_favre_noalloc(C.byref(g), fa, nf, pr, pu, oa,
+                                         C.byref(cp) if cp is not None else None, st, device,
+                                         C.c_void_p(stream.cuda_stream)))
+    return [s.as_dict() for s in st] if stats else None
 
 
 def _outputs_need(d, n):
