@@ -302,6 +302,64 @@ int kcf_kc_mp(kcf_ctx *ctx, const kcf_grid *grid, const kcf_filter *filter, cons
               const float *u, const kcf_kc_params *kp, float *m_sgs, float *m_ce, float *k_sgs,
               float *nu_t_eff, float *omega_sgs, kcf_kc_stats *stats);
 
+/* ---- D3Q27 lattice-Boltzmann solver with the kinetic closures -------------------------
+ * One collide-and-stream step of the paper's solver (App. "Lattice-Boltzmann discretization"
+ * and App. "Common operational algorithm") on a periodic lattice, in lattice units
+ * (Delta x = Delta t = 1, lattice velocities xi_i in {-1, 0, 1}^3, theta_R = 1/3; grid->h is
+ * not used). Populations are the time-shifted populations of eq.
+ * shifted_population_definition, float32 [27][N] blocks in the population order of
+ * kcf_sgs_carrier (i = 9 (c_x + 1) + 3 (c_y + 1) + (c_z + 1)).
+ * Per node: rho = sum_i f_i, rho u = sum_i f_i xi_i; the product equilibrium f0 (eq.
+ * discrete_equilibrium); S from central differences of u (eqs. fd, strain_rate_discrete);
+ * the closure's SGS trace; k_sgs = |m_aa| / 2 (reference density 1), nu_t_eff =
+ * max(nu, C_nu sqrt(k_sgs)) (Delta = Delta x), omega_sgs = (nu_t_eff / theta_R + 1/2)^-1
+ * (eq. omega_sgs_operational); omega = (nu / theta_R + 1/2)^-1 (eq. omega_t_discrete); the
+ * collision of the model; streaming f_i(x + xi_i, t + 1) = f_post_i(x, t) (eq. streaming). */
+typedef enum {
+  KCF_LBM_BGK = 0,       /* resolved BGK: f_post = f - omega (f - f0) */
+  KCF_LBM_KCRB = 1,      /* KC-RB, Hermite first-order part (eqs. kcrb_operational_fone,
+                            kcrb_operational_msgstrace, kcrb_operational_collision) */
+  KCF_LBM_KCRB_RAW = 2,  /* KC-RB with the raw xi xi first-order part of the paper's runs
+                            (eq. kcrb_operational_raw_fone) */
+  KCF_LBM_KCMP = 3,      /* KC-MP (eqs. kcmp_operational_msgstrace, kcmp_operational_collision) */
+  KCF_LBM_KCRR = 4       /* KC-RR (eqs. kcrr_operational_second_order_collision,
+                            kcrr_operational_high_order_collision,
+                            kcrr_operational_post_population, RR recursion eq. kcrr_rr) */
+} kcf_lbm_model;
+
+typedef struct {
+  int model;     /* kcf_lbm_model */
+  double nu;     /* molecular kinematic viscosity, lattice units (> 0) */
+  double c_nu;   /* closure constant C_nu (>= 0; the paper uses 0.02 for KC-RB and KC-RR,
+                    0.035 for KC-MP); 0 makes every closure the BGK step */
+} kcf_lbm_params;
+
+/* FP64 sums over the nodes of the state entering the step (reduced on the GPU). */
+typedef struct {
+  double mass;             /* sum rho */
+  double momentum[3];      /* sum rho u */
+  double kinetic_energy;   /* sum rho |u|^2 / 2 */
+  double mean_omega_sgs;   /* <omega_sgs> (omega for BGK) */
+  double clip_fraction;    /* fraction of nodes with C_nu sqrt(k_sgs) <= nu (1 for BGK) */
+  double mean_k_sgs;       /* <k_sgs> */
+  int64_t n_nodes;
+  double raw[8];           /* the raw sums */
+} kcf_lbm_stats;
+
+/* Equilibrium populations f_out [27][N] of density rho [N] and velocity u [3][N] (lattice
+ * units), e.g. to start a run. Asynchronous. Errors: KCF_EINVAL for NULL arguments or a bad
+ * grid. */
+int kcf_lbm_equilibrium(kcf_ctx *ctx, const kcf_grid *grid, const float *rho, const float *u,
+                        float *f_out);
+
+/* One time step from f_in to f_out (distinct device buffers [27][N], both owned by the
+ * caller). stats (host, may be NULL) receives sums of the state f_in; with stats the call
+ * synchronises, without it is asynchronous. One kernel launch (timed when timing is on).
+ * Errors: KCF_EINVAL for NULL arguments, f_in == f_out, an unknown model, nu <= 0, c_nu < 0 or
+ * n < 3; KCF_ENOMEM when the statistics records cannot be allocated. */
+int kcf_lbm_step(kcf_ctx *ctx, const kcf_grid *grid, const kcf_lbm_params *params,
+                 const float *f_in, float *f_out, kcf_lbm_stats *stats);
+
 /* E_k, enstrophy and <rho> of the unfiltered input (synchronises). */
 int kcf_input_stats(kcf_ctx *ctx, const kcf_grid *grid, const float *rho, const float *u,
                     kcf_input_summary *out);

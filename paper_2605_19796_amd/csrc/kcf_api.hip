@@ -713,6 +713,82 @@ int kcf_filter_favre_noalloc(const kcf_grid* grid, const kcf_filter* filters, in
   return KCF_OK;
 }
 
+int kcf_lbm_equilibrium(kcf_ctx* c, const kcf_grid* grid, const float* rho, const float* u,
+                        float* f_out) {
+  if (!c) return fail(KCF_EINVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!rho || !u || !f_out) return fail(KCF_EINVAL, "NULL argument");
+  KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  const int64_t n = (int64_t)grid->nx * grid->ny * grid->nz;
+  hipError_t e = launch_lbm_equilibrium(rho, u, f_out, n, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "equilibrium launch");
+  return KCF_OK;
+}
+
+int kcf_lbm_step(kcf_ctx* c, const kcf_grid* grid, const kcf_lbm_params* p, const float* f_in,
+                 float* f_out, kcf_lbm_stats* stats) {
+  if (!c) return fail(KCF_EINVAL, "ctx is NULL");
+  int rc = check_grid(grid);
+  if (rc) return rc;
+  if (!p || !f_in || !f_out) return fail(KCF_EINVAL, "NULL argument");
+  if (f_in == f_out) return fail(KCF_EINVAL, "f_in and f_out must be distinct buffers");
+  if (p->model < KCF_LBM_BGK || p->model > KCF_LBM_KCRR) return fail(KCF_EINVAL, "unknown model");
+  if (!(p->nu > 0.0) || !std::isfinite(p->nu)) return fail(KCF_EINVAL, "nu must be > 0");
+  if (!(p->c_nu >= 0.0) || !std::isfinite(p->c_nu)) return fail(KCF_EINVAL, "c_nu must be >= 0");
+  const int64_t ntot = (int64_t)grid->nx * grid->ny * grid->nz;
+  KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  LbmArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.fin = f_in;
+  A.fout = f_out;
+  A.nx = grid->nx;
+  A.ny = grid->ny;
+  A.nz = grid->nz;
+  A.ntot = ntot;
+  A.ntx = (grid->nx + lbm_tile_x() - 1) / lbm_tile_x();
+  A.nty = (grid->ny + lbm_tile_y() - 1) / lbm_tile_y();
+  A.ntiles = A.ntx * A.nty;
+  A.nzc = choose_zchunks(A.ntiles, grid->nz, 0, 2);
+  A.zlen = (grid->nz + A.nzc - 1) / A.nzc;
+  A.nzc = (grid->nz + A.zlen - 1) / A.zlen;
+  A.items_per_xcd = (A.ntiles * A.nzc + 7) / 8;
+  const double tau_hat = p->nu * 3.0 + 0.5;  // nu / theta_R + dt / 2, theta_R = 1/3
+  A.tau_hat = (float)tau_hat;
+  A.omega = (float)(1.0 / tau_hat);
+  A.nu = (float)p->nu;
+  A.c_nu = (float)p->c_nu;
+  A.model = p->model;
+  const int64_t nrec = (int64_t)A.ntiles * A.nzc * lbm_records_per_block();
+  if (stats) {
+    if (nrec > INT32_MAX) return fail(KCF_EUNSUPPORTED, "grid too large for statistics");
+    if ((rc = ensure_partials(c, (size_t)nrec * kLbmStat))) return rc;
+    A.partials = c->d_part;
+  }
+  if ((rc = timed_begin(c))) return rc;
+  hipError_t e = launch_lbm_step(A, 8 * A.items_per_xcd, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "lattice-Boltzmann step launch");
+  if ((rc = timed_end(c))) return rc;
+  if (stats) {
+    e = launch_reduce(c->d_part, (int)nrec, kLbmStat, c->d_sums, c->d_red, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    KCF_HIP(hipMemcpyAsync(c->h_sums, c->d_sums, sizeof(double) * kLbmStat,
+                           hipMemcpyDeviceToHost, c->stream), "stats copy");
+    KCF_HIP(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    const double* raw = c->h_sums;
+    std::memset(stats, 0, sizeof(*stats));
+    std::memcpy(stats->raw, raw, sizeof(double) * kLbmStat);
+    stats->n_nodes = ntot;
+    stats->mass = raw[0];
+    for (int a = 0; a < 3; ++a) stats->momentum[a] = raw[1 + a];
+    stats->kinetic_energy = raw[4];
+    stats->mean_omega_sgs = raw[5] / (double)ntot;
+    stats->clip_fraction = raw[6] / (double)ntot;
+    stats->mean_k_sgs = raw[7] / (double)ntot;
+  }
+  return KCF_OK;
+}
+
 int kcf_sgs_carrier(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filter, const float* rho,
                     const float* u, float* f_sgs, float* f_h2, kcf_carrier_stats* stats) {
   if (!c) return fail(KCF_EINVAL, "ctx is NULL");

@@ -160,6 +160,31 @@ int mono_records_per_block(int set);         // statistics records per x-y workg
 hipError_t launch_mono_z(const MonoArgs& a, int set, int R, int fp64, hipStream_t s);
 hipError_t launch_mono_xy(const MonoArgs& a, int set, int R, int fp64, hipStream_t s);
 
+// D3Q27 lattice-Boltzmann step (kcf_lbm.hip)
+constexpr int kLbmBgk = 0, kLbmKcrb = 1, kLbmKcrbRaw = 2, kLbmKcmp = 3, kLbmKcrr = 4;
+constexpr int kLbmStat = 8;  // FP64 sums: rho, rho u (3), rho |u|^2 / 2, omega_sgs, clipped, k_sgs
+struct LbmArgs {
+  const float* fin;        // populations [27][N] at time t
+  float* fout;             // populations [27][N] at time t + 1 (distinct from fin)
+  int nx, ny, nz;
+  int64_t ntot;
+  int ntx, nty, ntiles;    // tiles of colliding columns
+  int nzc, zlen;           // z chunks and their length
+  int items_per_xcd;       // (z-chunk, tile) items of one XCD's band
+  float omega;             // shifted molecular rate (nu / theta + 1/2)^-1
+  float tau_hat;           // 1 / omega
+  float nu;                // molecular viscosity (lattice units)
+  float c_nu;              // closure constant C_nu (Delta = 1)
+  int model;               // kLbm*
+  double* partials;        // [records][kLbmStat] or NULL
+};
+int lbm_tile_x();
+int lbm_tile_y();
+int lbm_records_per_block();
+hipError_t launch_lbm_step(const LbmArgs& a, int nblocks, hipStream_t s);
+hipError_t launch_lbm_equilibrium(const float* rho, const float* u, float* f, int64_t n,
+                                  hipStream_t s);
+
 // box kernels (kcf_box.hip)
 struct BoxGeom {
   int tile_x, tile_y;  // output columns of a tile

@@ -89,6 +89,23 @@ class KcStats(C.Structure):
     as_dict = WidthStats.as_dict
 
 
+class LbmParams(C.Structure):
+    _fields_ = [("model", C.c_int), ("nu", C.c_double), ("c_nu", C.c_double)]
+
+
+class LbmStats(C.Structure):
+    _fields_ = [("mass", C.c_double), ("momentum", C.c_double * 3), ("kinetic_energy", C.c_double),
+                ("mean_omega_sgs", C.c_double), ("clip_fraction", C.c_double),
+                ("mean_k_sgs", C.c_double), ("n_nodes", C.c_int64), ("raw", C.c_double * 8)]
+
+    as_dict = WidthStats.as_dict
+
+
+LBM_BGK, LBM_KCRB, LBM_KCRB_RAW, LBM_KCMP, LBM_KCRR = range(5)
+LBM_MODELS = {"bgk": LBM_BGK, "kcrb": LBM_KCRB, "kcrb_raw": LBM_KCRB_RAW, "kcmp": LBM_KCMP,
+              "kcrr": LBM_KCRR}
+
+
 class InputSummary(C.Structure):
     _fields_ = [("mean_rho", C.c_double), ("ek", C.c_double), ("enstrophy", C.c_double),
                 ("n_nonfinite", C.c_int64)]
@@ -125,6 +142,10 @@ _SIGS = {
     "kcf_kc_mp": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.POINTER(Filter), C.c_void_p,
                             C.c_void_p, C.POINTER(KcParams), C.c_void_p, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_void_p, C.POINTER(KcStats)]),
+    "kcf_lbm_equilibrium": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
+    "kcf_lbm_step": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.POINTER(LbmParams), C.c_void_p,
+                               C.c_void_p, C.POINTER(LbmStats)]),
     "kcf_input_stats": (C.c_int, [C.c_void_p, C.POINTER(Grid), C.c_void_p, C.c_void_p,
                                   C.POINTER(InputSummary)]),
     "kcf_reduce_check": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
@@ -428,6 +449,39 @@ class Context:
         st = KcStats() if stats else None
         check(self._lib.kcf_kc_mp(self.handle, C.byref(g), C.byref(fl), pr, pu, C.byref(kp), *outs,
                                   C.byref(st) if stats else None))
+        return st.as_dict() if stats else None
+
+    def lbm_equilibrium(self, rho, u, f_out=None):
+        """Equilibrium populations (27, nz, ny, nx) of rho (nz, ny, nx) and u (3, nz, ny, nx),
+        lattice units."""
+        import torch
+        nz, ny, nx = _grid3(rho)
+        n = nx * ny * nz
+        _need((rho, n, "rho"), (u, 3 * n, "u"), (f_out, 27 * n, "f_out"))
+        if f_out is None:
+            f_out = torch.empty((27, nz, ny, nx), dtype=torch.float32, device=rho.device)
+        g = Grid(nx, ny, nz, 1.0)
+        check(self._lib.kcf_lbm_equilibrium(self.handle, C.byref(g), _ptr(rho), _ptr(u),
+                                            _ptr(f_out)))
+        return f_out
+
+    def lbm_step(self, f_in, f_out, model, nu, c_nu, stats=True):
+        """One D3Q27 collide-and-stream step f_in -> f_out ((27, nz, ny, nx) device float32,
+        distinct); model is a name of LBM_MODELS or its number. Returns the statistics of the
+        state f_in (dict) or None."""
+        if f_in is None or f_in.dim() != 4 or f_in.shape[0] != 27:
+            raise ValueError("f_in: expected a (27, nz, ny, nx) tensor")
+        nz, ny, nx = (int(v) for v in f_in.shape[1:])
+        n = nx * ny * nz
+        _need((f_out, 27 * n, "f_out"))
+        if f_out is None or f_out.data_ptr() == f_in.data_ptr():
+            raise ValueError("f_out must be a distinct buffer")
+        m = LBM_MODELS[model] if isinstance(model, str) else int(model)
+        g = Grid(nx, ny, nz, 1.0)
+        p = LbmParams(m, nu, c_nu)
+        st = LbmStats() if stats else None
+        check(self._lib.kcf_lbm_step(self.handle, C.byref(g), C.byref(p), _ptr(f_in), _ptr(f_out),
+                                     C.byref(st) if stats else None))
         return st.as_dict() if stats else None
 
     def input_stats(self, rho, u, h):
