@@ -1,26 +1,27 @@
 """Throughput of the filtering path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-learned]
-                    [--no-carrier]
+                    [--no-carrier] [--no-lbm] [--no-c2]
 
 Workload: 512^3 periodic grid of synthetic spectral turbulence (u_rms 0.3, k0 16,
 rho = 1 + 0.2 s), FP32 fields resident in HBM; one step = four box-filter widths (2h, 4h,
-8h, 16h), one kernel launch each, every launch computing: products, separable periodic
-filter, Favre velocity, SGS stress tau (all written), central-difference gradient,
-gradient-model and Smagorinsky closures (on chip), FP64 statistics per width (SGS
-dissipation, tau-closure correlations) read back to the host; plus the input's E_k and
-enstrophy.
+8h, 16h) in one call, every width computing: products, separable periodic filter, Favre
+velocity, SGS stress tau (all written), central-difference gradient, gradient-model and
+Smagorinsky closures (on chip), FP64 statistics per width (SGS dissipation, tau-closure
+correlations) read back to the host; plus the input's E_k and enstrophy.
 
 Prints one JSON line. `value` is grid points per second (each point filtered at all four
-widths). `roofline` is for the kernel with the largest share of the step: algorithmic bytes
-of one launch (inputs 16 B + outputs 40 B per point) over its average HIP-event time on the
-stream it runs on.
+widths). `roofline` is for the kernel with the largest share of the step: the algorithmic
+bytes of the four-width step, 176 B per point (inputs 16 B once, 40 B of outputs per width),
+spread over its four launches (44 B per point each), over that kernel's average HIP-event
+time on the stream it runs on; `roofline.step` gives the same 176 B per point over the summed
+kernel time of the step, and `stream_ceiling` the time of a plain streaming kernel that reads
+4 and writes 40 fields of the same size (the practical HBM floor of the step on the device).
 
-Further sections of the same line: `carrier`, the a priori D3Q27 SGS carrier (f_sgs and its
-second-order Hermite reconstruction, stored, with statistics) on the 512^3 field at box 4h
-and 8h and on the 256^3 Gaussian-8h field; `moment3`, the third-order SGS moment and the
-Favre temperature on the 512^3 field with a spectral temperature; `kc_mp`, the a priori KC-MP
-SGS moment and relaxation-rate field against the exact tau on the 512^3 field; `learned`,
+Further sections of the same line: `c2`, the 256^3 Gaussian-8h call with the full output set;
+`carrier`, the a priori D3Q27 SGS carrier; `moment3`, the third-order SGS moment and the Favre
+temperature; `kc_mp`, the a priori KC-MP SGS moment and relaxation-rate field; `lbm`, the D3Q27
+collide-and-stream step of the Taylor-Green vortex with the kinetic closures; `learned`,
 training and the learned-vs-plain race.
 
 Profiling modes (for rocprofv3 runs): --profile-run times a few steps and skips the CPU
@@ -41,8 +42,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_POINT = 16 + 40  # one width: read rho, u; write rho_bar, ut, tau
 WIDTHS = (2, 4, 8, 16)
+BYTES_STEP = 16 + 40 * len(WIDTHS)  # read rho, u once; write rho_bar, ut, tau per width
+BYTES_PER_LAUNCH = BYTES_STEP / len(WIDTHS)  # the step's bytes spread over its four launches
 # kernel instance each width launches in the timed step (radius n/2; FP64 sums up to 4h;
 # Favre fields and statistics, no optional gradient-epilogue outputs)
 KERNELS = {2: "k_box1<1, double, 0>", 4: "k_box1<2, double, 0>",
@@ -75,20 +77,49 @@ def load_traffic(kernel):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(rho, u, n_sub=192):
-    """The FP64 oracle on a 192^3 periodic sub-cube of the same field, four widths."""
-    import numpy as np
+def _oracle_worker(job):
+    """One process of the CPU baseline: the FP64 oracle's full path at every width on one
+    periodic sub-cube (run with one numpy thread)."""
+    import time as _t
     from oracle import fields as F
-    r = rho[:n_sub, :n_sub, :n_sub].cpu().numpy()
-    uu = u[:, :n_sub, :n_sub, :n_sub].cpu().numpy()
-    h = 2 * math.pi / rho.shape[0]
-    t0 = time.perf_counter()
+    r, uu, h = job
+    t0 = _t.perf_counter()
     for nd in WIDTHS:
         F.full_path(r, uu, F.BOX, nd, h)
-    dt = time.perf_counter() - t0
-    return dict(value=n_sub ** 3 / dt, unit="points/s", cores=1, kind="oracle",
-                sample=f"numpy FP64 oracle, full path at 4 box widths on a {n_sub}^3 periodic "
-                       f"sub-cube of the 512^3 field ({dt:.1f} s, single thread)")
+    return _t.perf_counter() - t0
+
+
+def cpu_baseline(rho, u, n_sub=128):
+    """The FP64 oracle on the host cores: one 128^3 periodic sub-cube of the field per process,
+    every process running the full path at the four widths; points/s = processes x 128^3 /
+    wall time. Processes: the host's cores, at most 16 (the CPU share of one GPU)."""
+    import multiprocessing as mp
+    nproc = max(1, min(os.cpu_count() or 1, 16))
+    n = rho.shape[0]
+    h = 2 * math.pi / n
+    jobs = []
+    for p in range(nproc):
+        z0 = (p * n_sub) % (n - n_sub + 1)
+        y0 = ((p // 4) * n_sub) % (n - n_sub + 1)
+        jobs.append((rho[z0:z0 + n_sub, y0:y0 + n_sub, :n_sub].cpu().numpy().copy(),
+                     u[:, z0:z0 + n_sub, y0:y0 + n_sub, :n_sub].cpu().numpy().copy(), h))
+    env_old = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"  # inherited by the spawned workers
+    try:
+        ctx = mp.get_context("spawn")
+        t0 = time.perf_counter()
+        with ctx.Pool(nproc) as pool:
+            per = pool.map(_oracle_worker, jobs)
+        dt = time.perf_counter() - t0
+    finally:
+        if env_old is None:
+            os.environ.pop("OMP_NUM_THREADS", None)
+        else:
+            os.environ["OMP_NUM_THREADS"] = env_old
+    return dict(value=nproc * n_sub ** 3 / dt, unit="points/s", cores=nproc, kind="oracle",
+                sample=f"numpy FP64 oracle, full path at the 4 box widths on one {n_sub}^3 periodic "
+                       f"sub-cube of the 512^3 field per process, {nproc} processes of one thread "
+                       f"({dt:.1f} s wall, {max(per):.1f} s slowest process)")
 
 
 def progress(msg):
@@ -329,6 +360,121 @@ def kc_section(ctx, rho, u, args):
     return out
 
 
+C2_BYTES_PER_POINT = 16 + 100  # read rho, u; write rho_bar, ut, tau, grad, tau_gm (25 floats)
+
+
+def c2_section(ctx, args):
+    """256^3 Gaussian filter 8h with the full output set (rho_bar, ut, tau, grad, tau_gm) and
+    the FP64 statistics: the x-y pass into the slab buffer, the z pass with Favre division, then
+    the gradient/closure pass, timed together as one call."""
+    import torch
+    from paper_2605_19796_amd import kcf, synth
+    dev = torch.device("cuda", 0)
+    rho, u = synth.workload_fields("c256_gauss8", device=dev)
+    n = rho.shape[0]
+    h = 2 * math.pi / n
+    outs = [kcf.alloc_outputs((n, n, n), dev, ("rho_bar", "ut", "tau", "grad", "tau_gm"))]
+    filt = [(kcf.GAUSS, 8)]
+    progress("c2: 256^3 Gaussian 8h")
+    ctx.filter_favre(rho, u, h, filt, outs)
+    reps = 3 if args.profile_run else 10
+    ctx.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        st = ctx.filter_favre(rho, u, h, filt, outs)
+    t1 = time.perf_counter()
+    kt = ctx.kernel_times()
+    ctx.enable_timing(False)
+    ms_call = (t1 - t0) * 1e3 / reps
+    k_ms = sum(kt) / reps
+    pts = float(n) ** 3
+    gbs = C2_BYTES_PER_POINT * pts / (k_ms * 1e-3) / 1e9
+    out = {"workload": "256^3 spectral turbulence (k0 8, rho amplitude 0.2), Gaussian filter 8h, "
+                       "outputs rho_bar, ut, tau, grad, tau_gm and FP64 statistics",
+           "ms_per_call": ms_call, "kernel_ms": k_ms, "points_per_s": pts / (ms_call * 1e-3),
+           "bytes_per_point": C2_BYTES_PER_POINT, "achieved_gbs": gbs,
+           "hbm_frac": gbs / HBM_PEAK_GBS, "pi": st[0]["pi"], "corr_tau_gm": st[0]["corr_tau_gm"]}
+    del rho, u, outs
+    torch.cuda.empty_cache()
+    return out
+
+
+LBM_BYTES_PER_NODE = 2 * 27 * 4  # read and write the 27 FP32 populations
+
+
+def lbm_section(ctx, args):
+    """D3Q27 collide-and-stream of the Taylor-Green vortex (Re 1600, Ma 0.2: u0 = 0.2 c_s,
+    nu = u0 (N / 2 pi) / 1600) on a 256^3 lattice, one timed kernel per step, for the resolved
+    BGK step and the kinetic closures (C_nu 0.02 for KC-RB and KC-RR, 0.035 for KC-MP)."""
+    import torch
+    from paper_2605_19796_amd import kcf, synth
+    n = args.lbm_n
+    u0 = 0.2 / math.sqrt(3.0)
+    nu = u0 * (n / (2 * math.pi)) / 1600.0
+    rho_np, u_np = synth.taylor_green(n, u0=u0, rho_fluct=3.0 * u0 * u0 / 16.0)
+    dev = torch.device("cuda", 0)
+    rho = torch.from_numpy(rho_np).to(dev)
+    u = torch.from_numpy(u_np).to(dev)
+    f0 = ctx.lbm_equilibrium(rho, u)
+    a = torch.empty_like(f0)
+    b = torch.empty_like(f0)
+    del rho, u
+    steps = 4 if args.profile_run else 20
+    out = {"workload": f"Taylor-Green vortex on a {n}^3 lattice, Re 1600, Ma 0.2 (lattice units, "
+                       f"nu {nu:.5g})", "bytes_per_node": LBM_BYTES_PER_NODE}
+    nodes = float(n) ** 3
+    for model, c_nu in (("bgk", 0.0), ("kcrb_raw", 0.02), ("kcmp", 0.035), ("kcrr", 0.02)):
+        progress(f"lbm {model}")
+        a.copy_(f0)
+        st0 = ctx.lbm_step(a, b, model, nu, c_nu)
+        a, b = b, a
+        ctx.enable_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.lbm_step(a, b, model, nu, c_nu, stats=False)
+            a, b = b, a
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt = ctx.kernel_times()
+        ctx.enable_timing(False)
+        st1 = ctx.lbm_step(a, b, model, nu, c_nu)
+        k_ms = sum(kt) / len(kt)
+        gbs = LBM_BYTES_PER_NODE * nodes / (k_ms * 1e-3) / 1e9
+        out[model] = {
+            "c_nu": c_nu, "ms_per_step": (t1 - t0) * 1e3 / steps, "kernel_ms": k_ms,
+            "lattice_updates_per_s": nodes / (k_ms * 1e-3), "achieved_gbs": gbs,
+            "hbm_frac": gbs / HBM_PEAK_GBS,
+            "relative_mass_drift": (st1["mass"] - st0["mass"]) / st0["mass"],
+            "kinetic_energy_ratio": st1["kinetic_energy"] / st0["kinetic_energy"],
+            "mean_omega_sgs": st1["mean_omega_sgs"], "clip_fraction": st1["clip_fraction"],
+        }
+    del a, b, f0
+    torch.cuda.empty_cache()
+    return out
+
+
+def stream_ceiling(ctx, n):
+    """Time of kcf_stream_probe reading 4 and writing 40 fields of n^3 floats: the bytes of
+    the four-width step moved by a kernel that does nothing else."""
+    import torch
+    inp = torch.ones((4, n, n, n), dtype=torch.float32, device="cuda")
+    out = torch.empty((40, n, n, n), dtype=torch.float32, device="cuda")
+    ctx.stream_probe(inp, out)
+    ctx.enable_timing(True)
+    for _ in range(5):
+        ctx.stream_probe(inp, out)
+    kt = ctx.kernel_times()
+    ctx.enable_timing(False)
+    ms = sum(kt) / len(kt)
+    del inp, out
+    torch.cuda.empty_cache()
+    gbs = BYTES_STEP * float(n) ** 3 / (ms * 1e-3) / 1e9
+    return {"kernel": "kcf_stream_probe (4 fields in, 40 out)", "ms": ms, "gbs": gbs,
+            "frac_of_peak": gbs / HBM_PEAK_GBS}
+
+
 def copy_calibration():
     """One plain device-to-device copy of COPY_BYTES, for scaling FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -356,6 +502,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--learned-n", type=int, default=1024, help="grid of the learned-vs-plain race")
     ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--no-lbm", action="store_true")
+    ap.add_argument("--no-c2", action="store_true")
+    ap.add_argument("--lbm-n", type=int, default=256, help="lattice of the lbm section")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the filtering path here is a single-GPU build; "
@@ -408,9 +557,13 @@ def main():
     avg = {w: sum(v) / len(v) for w, v in per_width.items()}
     dom = max(WIDTHS, key=lambda w: avg[w])
     kernel = KERNELS[dom]
-    bytes_launch = BYTES_PER_POINT * pts
+    bytes_launch = BYTES_PER_LAUNCH * pts
     achieved = bytes_launch / (avg[dom] * 1e-3) / 1e9
+    step_kernel_ms = sum(avg.values())
+    step_gbs = BYTES_STEP * pts / (step_kernel_ms * 1e-3) / 1e9
     traffic = load_traffic(kernel)
+    progress("streaming ceiling")
+    ceiling = stream_ceiling(ctx, n)
     line = {
         "metric": "filtered grid points/s (% HBM roofline); learned vs plain closure at fixed error",
         "value": value,
@@ -434,9 +587,13 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": kernel, "width_h": dom, "kernel_ms": avg[dom],
-            "bytes_per_launch": bytes_launch, "bytes_per_point": BYTES_PER_POINT,
+            "bytes_per_launch": bytes_launch, "bytes_per_point": BYTES_PER_LAUNCH,
             "kernel_ms_by_width": {f"{w}h": avg[w] for w in WIDTHS},
+            "step": {"bytes_per_point": BYTES_STEP, "kernel_ms": step_kernel_ms,
+                     "achieved": step_gbs, "frac": step_gbs / HBM_PEAK_GBS,
+                     "frac_by_ms_per_step": BYTES_STEP * pts / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         },
+        "stream_ceiling": ceiling,
         "stats": {
             f"{w}h": {"pi": s["pi"], "pi_gm": s["pi_gm"], "corr_tau_gm": s["corr_tau_gm"],
                       "corr_pi": s["corr_pi"]} for w, s in zip(WIDTHS, st)
@@ -448,10 +605,14 @@ def main():
         line["cpu_baseline"] = cpu_baseline(rho, u)
     del outs
     torch.cuda.empty_cache()
+    if not args.no_c2:
+        line["c2"] = c2_section(ctx, args)
     if not args.no_carrier:
         line["carrier"] = carrier_section(ctx, rho, u, args)
         line["moment3"] = moment3_section(ctx, rho, u, args)
         line["kc_mp"] = kc_section(ctx, rho, u, args)
+    if not args.no_lbm:
+        line["lbm"] = lbm_section(ctx, args)
     if not args.no_learned:
         del rho, u
         torch.cuda.empty_cache()

@@ -430,6 +430,15 @@ int kcf_mlp_infer_field(kcf_mlp *mlp, const kcf_grid *grid, const float *rho_bar
 int kcf_mlp_save(kcf_mlp *mlp, const char *path);
 int kcf_mlp_load(kcf_mlp *mlp, const char *path);
 
+/* ---- measurement aid ----------------------------------------------------------------- */
+/* Plain streaming kernel: out block j (n floats) = in block (j mod nin) times (j + 1), for
+ * nin <= 8 input and nout <= 64 output blocks of n floats (device, caller-owned). It moves the
+ * bytes of a call of the filtering path (4 fields in; 10 per width out) with no other work, so
+ * its time is the practical HBM floor of such a call on the device. Asynchronous, timed like
+ * the filter launches. Not part of the method. Errors: KCF_EINVAL for NULL or out-of-range
+ * arguments. */
+int kcf_stream_probe(kcf_ctx *ctx, const float *in, int nin, float *out, int nout, int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1025,4 +1025,16 @@ int kcf_reduce_check(kcf_ctx* c, const float* a, const float* b, int64_t n, doub
   return KCF_OK;
 }
 
+int kcf_stream_probe(kcf_ctx* c, const float* in, int nin, float* out, int nout, int64_t n) {
+  if (!c || !in || !out) return fail(KCF_EINVAL, "NULL argument");
+  if (nin < 1 || nin > 8 || nout < 1 || nout > 64 || n < 1)
+    return fail(KCF_EINVAL, "need 1 <= nin <= 8, 1 <= nout <= 64, n >= 1");
+  KCF_HIP(hipSetDevice(c->device), "hipSetDevice");
+  int rc = timed_begin(c);
+  if (rc) return rc;
+  hipError_t e = launch_stream_probe(in, nin, out, nout, n, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "stream probe launch");
+  return timed_end(c);
+}
+
 }  // extern "C"

@@ -303,6 +303,35 @@ hipError_t launch_reduce(const double* partials, int nparts, int nstat, double* 
   return hipGetLastError();
 }
 
+// Streaming reference: out block j = in block (j mod nin) times (j + 1), element by element;
+// nin fields read once and nout fields written once, with the access pattern of the filter
+// path's inputs and outputs and no other work.
+__global__ void __launch_bounds__(256) k_stream_probe(const float* __restrict__ in, int nin,
+                                                      float* __restrict__ out, int nout,
+                                                      int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < nin) v[k] = in[(int64_t)k * n + p];
+    for (int j = 0; j < nout; ++j) {
+      int k = j % nin;
+      float x = v[0];
+#pragma unroll
+      for (int q = 1; q < 8; ++q)
+        if (q == k) x = v[q];
+      out[(int64_t)j * n + p] = x * (float)(j + 1);
+    }
+  }
+}
+
+hipError_t launch_stream_probe(const float* in, int nin, float* out, int nout, int64_t n,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_stream_probe, dim3(8192), dim3(256), 0, s, in, nin, out, nout, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_check(const float* a, const float* b, int64_t n, double* partials,
                                int nblocks, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_check, dim3(nblocks), dim3(kCT), 0, s, a, b, n, partials);

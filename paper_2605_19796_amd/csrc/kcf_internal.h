@@ -99,6 +99,8 @@ hipError_t launch_reduce(const double* partials, int nparts, int nstat, double* 
                          double* scratch, hipStream_t s);
 hipError_t launch_reduce_check(const float* a, const float* b, int64_t n, double* partials,
                                int nblocks, hipStream_t s);
+hipError_t launch_stream_probe(const float* in, int nin, float* out, int nout, int64_t n,
+                               hipStream_t s);
 
 // general-tap kernels (kcf_taps.hip)
 constexpr size_t kTapBufferCap = (size_t)8 << 30;  // bytes of x-y filtered planes held at once

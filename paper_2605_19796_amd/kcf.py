@@ -150,6 +150,8 @@ _SIGS = {
                                   C.POINTER(InputSummary)]),
     "kcf_reduce_check": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
                                    C.POINTER(C.c_double)]),
+    "kcf_stream_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int,
+                                   C.c_int64]),
     "kcf_mlp_create": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p)]),
     "kcf_mlp_destroy": (None, [C.c_void_p]),
     "kcf_mlp_set_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_float)]),
@@ -493,6 +495,13 @@ class Context:
         s = InputSummary()
         check(self._lib.kcf_input_stats(self.handle, C.byref(g), pr, pu, C.byref(s)))
         return dict(mean_rho=s.mean_rho, ek=s.ek, enstrophy=s.enstrophy, n_nonfinite=s.n_nonfinite)
+
+    def stream_probe(self, inp, out):
+        """kcf_stream_probe on inp (nin, ...) and out (nout, ...) blocks of equal size."""
+        nin, nout = int(inp.shape[0]), int(out.shape[0])
+        n = inp[0].numel()
+        _need((inp, nin * n, "in"), (out, nout * n, "out"))
+        check(self._lib.kcf_stream_probe(self.handle, _ptr(inp), nin, _ptr(out), nout, n))
 
     def reduce_check(self, a, b=None):
         out = (C.c_double * 3)()
