@@ -3,9 +3,12 @@ BF16-emulating FP64 oracle, through the C ABI; training gain over the gradient m
 
 Tolerances: the GPU accumulates in FP32 and the oracle in FP64, so an activation lying within
 ~1e-6 of a BF16 rounding boundary can round to the neighbouring BF16 value on one side only;
-such flips change single activations by one BF16 step (2^-8 relative). Outputs are compared
-as max|gpu - oracle| / max|oracle| <= 1e-2 and gradients per tensor as
-||gpu - oracle||_F / ||oracle||_F <= 1e-2; the exact-input Adam update to 1e-6.
+such flips change single activations by one BF16 step (2^-8 relative). Gradients are compared
+per tensor as ||gpu - oracle||_F / ||oracle||_F <= 1e-3 (the gradient check of the
+specification); outputs as max|gpu - oracle| / max|oracle| <= 1e-2, the worst single point,
+where one flipped activation can shift an output by a few 1e-3, together with the RMS
+relative error <= 1e-3; the exact-input Adam update to 1e-6. Every assertion carries the
+measured error.
 """
 import math
 import os
@@ -22,7 +25,8 @@ from paper_2605_19796_amd import kcf, learned, synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 TOL_OUT = 1e-2
-TOL_GRAD = 1e-2
+TOL_GRAD = 1e-3
+TOL_RMS = 1e-3
 LAYERS = [("W1", 0, 896), ("b1", 896, 960), ("W2", 960, 5056), ("b2", 5056, 5120),
           ("W3", 5120, 9216), ("b3", 9216, 9280), ("W4", 9280, 9664), ("b4", 9664, 9670)]
 
@@ -86,12 +90,14 @@ def test_forward_matches_oracle(ctx):
     xs = std32(x, nm[:14], nm[14:28])
     yo, _ = M.forward(M.init_params(3), xs)
     err = np.max(np.abs(yg - yo)) / np.max(np.abs(yo))
-    say(f"[gpu]   forward rel err {err:.2e}")
-    assert err <= TOL_OUT
+    rms = np.sqrt(np.mean((yg - yo) ** 2) / np.mean(yo ** 2))
+    say(f"[gpu]   forward rel err max {err:.2e} rms {rms:.2e}")
+    assert err <= TOL_OUT, f"max relative error {err:.3e}"
+    assert rms <= TOL_RMS, f"rms relative error {rms:.3e}"
     m.close()
 
 
-@pytest.mark.parametrize("batch", [256, 4096])
+@pytest.mark.parametrize("batch", [256, 4096, 65536])
 def test_gradients_match_oracle(ctx, batch):
     say(f"[gpu] gradients vs oracle, batch {batch}")
     n = 3 * batch
@@ -105,14 +111,14 @@ def test_gradients_match_oracle(ctx, batch):
     xs = std32(x[idx], nm[:14], nm[14:28])
     ys = std32(y[idx], nm[28:34], nm[34:40])
     lo, go = M.loss_and_grads(M.init_params(5), xs, ys)
-    assert abs(loss - lo) <= 1e-3 * lo
+    assert abs(loss - lo) <= 1e-3 * lo, f"loss {loss} vs oracle {lo}"
     errs = {}
     for name, a, b in LAYERS:
         errs[name] = np.linalg.norm(g[a:b] - go[a:b]) / np.linalg.norm(go[a:b])
     say("[gpu]   rel Frobenius errors " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     m.close()
     for name, e in errs.items():
-        assert e <= TOL_GRAD, (name, e)
+        assert e <= TOL_GRAD, f"batch {batch}: {name} relative Frobenius error {e:.3e}"
 
 
 def test_adam_step(ctx):
@@ -307,3 +313,73 @@ def test_mlp_error_paths(ctx):
         m.set_params(p)
     assert e.value.code == kcf.EINVAL
     m.close()
+
+
+def test_c1024_inference_sampled(ctx):
+    """Learned inference over a 1024^3 field, the launch of the learned-vs-plain race
+    (rho_bar, ut -> tau with the envelope fallback to the gradient model), against the oracle
+    network at sampled points. The inputs are the synthetic 1024^3 density and velocity fields
+    themselves (the network does not need them to be filtered), so nothing the oracle sees
+    comes from the GPU: features, standardisation, envelope test and fallback at the sampled
+    points come from the oracle's own central differences of the input velocity."""
+    say("[gpu] 1024^3 learned inference: sampled parity")
+    n = 1024
+    h = 2 * math.pi / n
+    delta = 8 * h
+    w, _ = F.filter_weights(F.GAUSS, 8)
+    m2 = F.second_moment(w, h)
+    rho, u = synth.workload_fields("c1024_learned", device="cuda")
+    rng = np.random.default_rng(21)
+    pts = np.concatenate([np.array([[0, 0, 0], [n - 1, n - 1, n - 1], [n // 2, 7, n - 1]]),
+                          rng.integers(0, n, (253, 3))])
+
+    def grad_at(p):
+        """(npts, 3, 3) central-difference gradients G[a, b] = d_b u_a at points p (k, j, i)."""
+        k, j, i = (torch.as_tensor(p[:, c], device="cuda") for c in range(3))
+        G = np.empty((len(p), 3, 3))
+        for b, (dk, dj, di) in enumerate(((0, 0, 1), (0, 1, 0), (1, 0, 0))):
+            kp, jp, ip = (k + dk) % n, (j + dj) % n, (i + di) % n
+            km, jm, im = (k - dk) % n, (j - dj) % n, (i - di) % n
+            up = u[:, kp, jp, ip].cpu().numpy().astype(np.float64)
+            um = u[:, km, jm, im].cpu().numpy().astype(np.float64)
+            G[:, :, b] = ((up - um) / (2 * h)).T
+        return G
+
+    # normalisation from oracle features of 20 000 random points; a +-3 envelope
+    sample = rng.integers(0, n, (20000, 3))
+    fs = M.features_from_grad(grad_at(sample), delta)
+    mu, sd = M.norm_stats(fs)
+    nm = np.concatenate([mu, sd, np.full(6, 2e-3), np.full(6, 1e-3), np.full(14, -3.0),
+                         np.full(14, 3.0)]).astype(np.float32)
+    params = M.init_params(11)
+    m = kcf.MLP(ctx)
+    m.set_params(params)
+    m.set_norm(nm)
+    mask = torch.zeros((n ** 3 + 15) // 16, dtype=torch.int16, device="cuda")
+    tau, nfb = m.infer_field(rho, u, h, delta, m2, mask_out=mask)
+    torch.cuda.synchronize()
+    G = grad_at(pts)
+    feats = M.features_from_grad(G, delta).astype(np.float32)
+    xs = std32(feats, nm[:14], nm[14:28]).astype(np.float64)
+    flag_o = ~np.all(np.isfinite(xs) & (xs >= nm[40:54]) & (xs <= nm[54:68]), axis=1)
+    idx = torch.as_tensor(pts, device="cuda", dtype=torch.long)
+    rb = rho[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy().astype(np.float64)
+    gm = np.stack([rb * m2 * np.einsum("pk,pk->p", G[:, a, :], G[:, b, :]) for (a, b) in F.PAIRS], 1)
+    yo, _ = M.forward(params, np.where(np.isfinite(xs), xs, 0.0))
+    tau_o = np.where(flag_o[:, None], gm, rb[:, None] * (nm[28:34] + nm[34:40] * yo))
+    flat = (idx[:, 0] * n + idx[:, 1]) * n + idx[:, 2]
+    bits = mask.view(torch.int16).cpu().numpy().view(np.uint16)
+    fl = flat.cpu().numpy()
+    flag_g = ((bits[fl // 16] >> (fl % 16)) & 1).astype(bool)
+    tg = tau[:, idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy().T.astype(np.float64)
+    say(f"[gpu]   fallback points {nfb} of {n ** 3}; sampled flags differ at "
+        f"{int(np.sum(flag_g != flag_o))} of {len(pts)}")
+    assert 0 < nfb < n ** 3
+    assert np.sum(flag_g != flag_o) <= 2
+    same = flag_g == flag_o
+    for c in range(6):
+        e = np.max(np.abs(tg[same, c] - tau_o[same, c])) / np.max(np.abs(tau_o[same, c]))
+        assert e <= TOL_OUT, f"component {c}: max relative error {e:.3e}"
+    m.close()
+    del rho, u, tau, mask
+    torch.cuda.empty_cache()
