@@ -2,18 +2,19 @@
 //
 // One launch performs one time step on a periodic lattice of FP32 populations stored as 27
 // blocks of N values (population i = 9 (c_x + 1) + 3 (c_y + 1) + (c_z + 1), node i + nx (j +
-// ny k)). A workgroup owns a 32 x 16 tile of node columns (30 x 14 collide, the ring of one
-// column around them only supplies velocities to the central differences) and marches along z:
+// ny k)). A workgroup owns a 34 x 15 tile of node columns (the 32 x 13 inner ones collide and
+// start on a 128-byte row boundary; the ring of one column around them only supplies
+// velocities to the central differences) and marches along z:
 //   * the 27 populations of the arriving plane are read once (coalesced rows) and kept in
 //     registers for one step; their density and velocity go to LDS (three plane slots, one
 //     barrier per step), so the plane behind has all six face neighbours' velocities;
-//   * the plane behind collides: f_neq = f - f0(rho, u) in population space (the product
-//     equilibrium), then its 27 Hermite coefficients by three 3-point transforms (D1Q3 basis
-//     1, xi, xi^2 - theta along each axis), the closure acts on the coefficients (the second-
-//     order block holds m_cneq; the 17 higher-order components of the tensor-product basis are
-//     the rest), and the change of the coefficients goes back through the inverse transforms
-//     as an increment added to the populations, so the small populations keep their relative
-//     precision;
+//   * the plane behind collides in place: f_neq = f - f0(rho, u) in population space (the
+//     product equilibrium), then its 27 Hermite coefficients by three 3-point transforms (D1Q3
+//     basis 1, xi, xi^2 - theta along each axis); the closure relaxes the coefficients (the
+//     second-order block holds m_cneq; the 17 higher-order components of the tensor-product
+//     basis are the rest; density and momentum belong to f0), and the relaxed coefficients go
+//     back through the inverse transforms and are added to f0, so every small population keeps
+//     its relative precision and 27 registers hold the whole node;
 //   * each post-collision population is pushed along its link to the output lattice.
 // Closures act on the coefficients as follows (omega = shifted molecular rate, omega_s the SGS
 // rate from the trace, m_CE = -2 rho theta tau_hat S):
@@ -32,8 +33,10 @@ namespace kcf {
 namespace {
 
 constexpr float kTh = 1.0f / 3.0f;
-constexpr int kLX = 32, kLY = 16, kLT = kLX * kLY;  // thread columns of a tile
+constexpr int kLX = 34, kLY = 15, kLT = kLX * kLY;  // thread columns of a tile (510)
 constexpr int kIX = kLX - 2, kIY = kLY - 2;         // colliding columns of a tile
+constexpr int kBT = 512;                            // threads: the columns and 2 spare
+constexpr int kWaves = kBT / 64;                    // waves of a workgroup
 
 __device__ __forceinline__ int wrapi(int i, int n) {
   int r = i % n;
@@ -93,8 +96,8 @@ struct NodeStat {  // FP64 sums per lane
   double s[kLbmStat];
 };
 
-// One node: populations f (in place), density, velocity and the strain S of the central
-// differences. Returns nothing; accumulates the node's statistics when `use`.
+// One node, in place: populations f, density, velocity and the strain S of the central
+// differences. Accumulates the node's statistics when `use`.
 template <int M>
 __device__ __forceinline__ void collide_node(float (&f)[27], float rho, const float (&u)[3],
                                              const float (&S)[3][3], const LbmArgs& A,
@@ -111,31 +114,26 @@ __device__ __forceinline__ void collide_node(float (&f)[27], float rho, const fl
     F[a][2] = side + l;
   }
   const float W1[3] = {1.0f / 6.0f, 2.0f / 3.0f, 1.0f / 6.0f};
-  float d[27];
+  auto f0 = [&](int px, int py, int pz) {
+    return rho * (W1[px] * W1[py] * W1[pz]) * F[0][px] * F[1][py] * F[2][pz];
+  };
 #pragma unroll
   for (int px = 0; px < 3; ++px)
 #pragma unroll
-    for (int py = 0; py < 3; ++py) {
-      const float wxy = rho * (W1[px] * W1[py]) * F[0][px] * F[1][py];
+    for (int py = 0; py < 3; ++py)
 #pragma unroll
-      for (int pz = 0; pz < 3; ++pz) {
-        const int i = 9 * px + 3 * py + pz;
-        d[i] = f[i] - wxy * W1[pz] * F[2][pz];
-      }
-    }
+      for (int pz = 0; pz < 3; ++pz) f[9 * px + 3 * py + pz] -= f0(px, py, pz);
+  float* d = f;
   forward(d);  // Hermite coefficients of f_neq; index 9 ax + 3 ay + az by degree
   const float tau_hat = A.tau_hat, om = A.omega;
-  // second-order block: raw moments of the massless f_neq
   const int i2[6] = {18, 6, 2, 12, 10, 4};   // xx yy zz xy xz yz
   const int pa[6] = {0, 1, 2, 0, 0, 1}, pb[6] = {0, 1, 2, 1, 2, 2};
-  float dn[27];
-#pragma unroll
-  for (int i = 0; i < 27; ++i) dn[i] = 0.0f;
   float oms = om, ksgs = 0.0f, clip = 1.0f;
-  if constexpr (M == kLbmBgk) {  // every coefficient of degree >= 2 (mass, momentum kept)
+  // density and momentum belong to f0: their coefficients of f_neq are rounding residue
+  d[0] = d[1] = d[3] = d[9] = 0.0f;
+  if constexpr (M == kLbmBgk) {  // every coefficient of degree >= 2 relaxes with omega
 #pragma unroll
-    for (int i = 0; i < 27; ++i)
-      if (i / 9 + (i / 3) % 3 + i % 3 >= 2) dn[i] = -om * d[i];
+    for (int i = 0; i < 27; ++i) d[i] *= 1.0f - om;
   } else {
     float mce[6];
     const float cce = -2.0f * rho * kTh * tau_hat;
@@ -150,9 +148,11 @@ __device__ __forceinline__ void collide_node(float (&f)[27], float rho, const fl
     clip = nut <= A.nu ? 1.0f : 0.0f;
     oms = 1.0f / fmaf(3.0f, nue, 0.5f);
     const float dr = oms - om;
+    // second order: (1 - omega) m_CE + (1 - omega_s)(m_cneq - m_CE)
 #pragma unroll
-    for (int s = 0; s < 6; ++s) dn[i2[s]] = fmaf(dr, mce[s], -oms * d[i2[s]]);
-    if constexpr (M == kLbmKcrbRaw) dn[0] = -dr * rho * tau_hat * trS;
+    for (int s = 0; s < 6; ++s) d[i2[s]] = fmaf(dr, mce[s], (1.0f - oms) * d[i2[s]]);
+    // the raw xi xi first-order part moves density: (omega - omega_s) rho tau_hat tr S
+    if constexpr (M == kLbmKcrbRaw) d[0] = -dr * rho * tau_hat * trS;
     // higher orders: every index with at least three letters (17 of them)
     float u2[3];
 #pragma unroll
@@ -167,9 +167,9 @@ __device__ __forceinline__ void collide_node(float (&f)[27], float rho, const fl
           if (n < 3) continue;
           const int i = 9 * ax + 3 * ay + az;
           if constexpr (M == kLbmKcmp) {
-            dn[i] = -om * d[i];
+            d[i] *= 1.0f - om;
           } else if constexpr (M == kLbmKcrb || M == kLbmKcrbRaw) {
-            dn[i] = -oms * d[i];
+            d[i] *= 1.0f - oms;
           } else {
             // RR reference of eq. kcrr_rr with the seed m_CE: a sum over the pairs of letters,
             // the pair carrying m_CE and the other letters a velocity each
@@ -197,13 +197,18 @@ __device__ __forceinline__ void collide_node(float (&f)[27], float rho, const fl
                   rr += p;
                 }
               }
-            dn[i] = fmaf(dr, rr, -oms * d[i]);
+            // (1 - omega) a_rr + (1 - omega_s)(d - a_rr)
+            d[i] = fmaf(dr, rr, (1.0f - oms) * d[i]);
           }
         }
   }
-  inverse(dn);
+  inverse(d);
 #pragma unroll
-  for (int i = 0; i < 27; ++i) f[i] += dn[i];
+  for (int px = 0; px < 3; ++px)
+#pragma unroll
+    for (int py = 0; py < 3; ++py)
+#pragma unroll
+      for (int pz = 0; pz < 3; ++pz) f[9 * px + 3 * py + pz] += f0(px, py, pz);
   if (use) {
     st.s[0] += (double)rho;
     st.s[1] += (double)(rho * u[0]);
@@ -256,14 +261,15 @@ __device__ __forceinline__ bool lbm_block(const LbmArgs& A, int& item) {
 }
 
 template <int M>
-__global__ void __launch_bounds__(kLT) k_lbm_step(LbmArgs A) {
-  __shared__ float su[3][3][kLT];  // velocity of three planes
+__global__ void __launch_bounds__(kBT) k_lbm_step(LbmArgs A) {
+  __shared__ float su[3][3][kBT];  // velocity of three planes (spare threads write their own slot)
   int item;
   if (!lbm_block(A, item)) return;
   const int tile = item % A.ntiles, zc = item / A.ntiles;
   const int tx = tile % A.ntx, ty = tile / A.ntx;
+  // threads past the 34 x 15 columns (cy == 15) load a wrapped column and never collide
   const int tid = threadIdx.x, cx = tid % kLX, cy = tid / kLX;
-  const int x0 = tx * kIX - 1, y0 = ty * kIY - 1;
+  const int x0 = tx * kIX - 1, y0 = ty * kIY - 1;  // column (0, 0): one left of the inner ones
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int gx = wrapi(x0 + cx, nx), gy = wrapi(y0 + cy, ny);
   const bool interior = cx >= 1 && cx <= kIX && cy >= 1 && cy <= kIY && x0 + cx < nx &&
@@ -288,6 +294,8 @@ __global__ void __launch_bounds__(kLT) k_lbm_step(LbmArgs A) {
     for (int i = 0; i < 27; ++i) f[i] = A.fin[(int64_t)i * ntot + zb];
   };
 
+  // populations of three planes per thread: the one behind (collides), the arriving one
+  // (moments) and the next one, requested a step ahead
   float fc[27], fp[27], fn[27];
   float rho_p = 1.0f, up[3] = {0.f, 0.f, 0.f}, upp[3] = {0.f, 0.f, 0.f};
   load_plane(fc, z0 - 1);
@@ -301,7 +309,7 @@ __global__ void __launch_bounds__(kLT) k_lbm_step(LbmArgs A) {
     moments(fc, rho_c, uc);
     float* slot = &su[k % 3][0][0];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) slot[a * kLT + tid] = uc[a];
+    for (int a = 0; a < 3; ++a) slot[a * kBT + tid] = uc[a];
     if (k + 1 < nk) load_plane(fn, zl + 1);
     lds_barrier();
     if (k >= 2 && interior) {
@@ -311,7 +319,7 @@ __global__ void __launch_bounds__(kLT) k_lbm_step(LbmArgs A) {
       float G[3][3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const float* ua = sp + a * kLT;
+        const float* ua = sp + a * kBT;
         G[a][0] = 0.5f * (ua[tid + 1] - ua[tid - 1]);
         G[a][1] = 0.5f * (ua[tid + kLX] - ua[tid - kLX]);
         G[a][2] = 0.5f * (uc[a] - upp[a]);
@@ -349,7 +357,7 @@ __global__ void __launch_bounds__(kLT) k_lbm_step(LbmArgs A) {
     }
   }
   if (A.partials) {  // per-wave record: fixed-order wave reduction of the lane sums
-    double* rec = A.partials + ((int64_t)item * (kLT / 64) + (tid >> 6)) * kLbmStat;
+    double* rec = A.partials + ((int64_t)item * kWaves + (tid >> 6)) * kLbmStat;
 #pragma unroll
     for (int s = 0; s < kLbmStat; ++s) {
       double r = st.s[s];
@@ -396,17 +404,17 @@ __global__ void __launch_bounds__(256) k_lbm_equilibrium(const float* rho, const
 
 int lbm_tile_x() { return kIX; }
 int lbm_tile_y() { return kIY; }
-int lbm_records_per_block() { return kLT / 64; }
+int lbm_records_per_block() { return kWaves; }
 
 hipError_t launch_lbm_step(const LbmArgs& a, int nblocks, hipStream_t s) {
   switch (a.model) {
-    case kLbmBgk: hipLaunchKernelGGL(k_lbm_step<kLbmBgk>, dim3(nblocks), dim3(kLT), 0, s, a); break;
-    case kLbmKcrb: hipLaunchKernelGGL(k_lbm_step<kLbmKcrb>, dim3(nblocks), dim3(kLT), 0, s, a); break;
+    case kLbmBgk: hipLaunchKernelGGL(k_lbm_step<kLbmBgk>, dim3(nblocks), dim3(kBT), 0, s, a); break;
+    case kLbmKcrb: hipLaunchKernelGGL(k_lbm_step<kLbmKcrb>, dim3(nblocks), dim3(kBT), 0, s, a); break;
     case kLbmKcrbRaw:
-      hipLaunchKernelGGL(k_lbm_step<kLbmKcrbRaw>, dim3(nblocks), dim3(kLT), 0, s, a);
+      hipLaunchKernelGGL(k_lbm_step<kLbmKcrbRaw>, dim3(nblocks), dim3(kBT), 0, s, a);
       break;
-    case kLbmKcmp: hipLaunchKernelGGL(k_lbm_step<kLbmKcmp>, dim3(nblocks), dim3(kLT), 0, s, a); break;
-    case kLbmKcrr: hipLaunchKernelGGL(k_lbm_step<kLbmKcrr>, dim3(nblocks), dim3(kLT), 0, s, a); break;
+    case kLbmKcmp: hipLaunchKernelGGL(k_lbm_step<kLbmKcmp>, dim3(nblocks), dim3(kBT), 0, s, a); break;
+    case kLbmKcrr: hipLaunchKernelGGL(k_lbm_step<kLbmKcrr>, dim3(nblocks), dim3(kBT), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

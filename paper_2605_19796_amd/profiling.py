@@ -80,7 +80,8 @@ def traffic(args):
     w_avg = sum(write) / len(write)
     res = {
         "kernel": args.kernel,
-        "workload": "512^3 box filter path (bench.py --profile-run)",
+        "workload": "512^3 four-width box filter step (bench.py --profile-run); algorithmic bytes "
+                    "per launch: the step's 176 B per point spread over its four launches",
         "kernel_source_sha256_16": bench.kernel_source_hash(),
         "fetch_counter_avg": f_avg, "write_counter_avg": w_avg,
         "dispatches": [len(fetch), len(write)],
@@ -90,7 +91,7 @@ def traffic(args):
         "fetch_bytes_per_launch": f_avg * kf,
         "write_bytes_per_launch": w_avg * kw,
         "bytes_per_launch": f_avg * kf + w_avg * kw,
-        "algorithmic_bytes_per_launch": bench.BYTES_PER_POINT * 512 ** 3,
+        "algorithmic_bytes_per_launch": bench.BYTES_PER_LAUNCH * 512 ** 3,
         "commands": args.commands,
     }
     if args.rdreq and args.cal_rdreq:
