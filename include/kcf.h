@@ -169,7 +169,9 @@ typedef struct {
 int kcf_version(void);  /* 10000 * major + 100 * minor + patch */
 
 /* Create a context on HIP device `device` that enqueues on `stream` (hipStream_t, NULL =
- * default stream). The context owns only scratch memory for reductions. */
+ * default stream). The context owns its scratch memory: the FP64 partial sums of the
+ * reductions and, grown on demand and kept until kcf_ctx_destroy, the slab and field buffers
+ * of the multi-kernel paths. */
 int kcf_ctx_create(kcf_ctx **out, int device, void *stream);
 int kcf_ctx_set_stream(kcf_ctx *ctx, void *stream);
 void kcf_ctx_destroy(kcf_ctx *ctx);
@@ -203,8 +205,9 @@ int kcf_filter_taps(int kind, int delta_over_h, double h, float *w, int cap, int
  * and closures are evaluated only for the fields outs[f] asks for (none for rho_bar, ut and
  * tau alone).
  * Box widths up to 16h (FP32) or 8h (FP64) run as one fused kernel per width. Other widths
- * (Gaussian, wider box) run as an x-y pass into a context buffer of at most 8 GiB of
- * filtered products (the whole field or z slabs), a z pass writing rho_bar, ut, tau, and,
+ * (Gaussian, wider box) run as an x-y pass into a context buffer of filtered products (the
+ * whole field or z slabs; 8 GiB, raised up to 48 GiB while half of the free device memory
+ * stays free; the outputs do not depend on the slab count), a z pass writing rho_bar, ut, tau, and,
  * when the gradient is needed, the pass of kcf_grad_closure on those fields; if the caller
  * does not ask for rho_bar, ut or tau the context holds them in a scratch of 10 N floats.
  * Errors: KCF_EINVAL for null rho/u/outs/grid, n < 3 in any direction, n_filters outside

@@ -590,7 +590,7 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     T.ny = grid->ny;
     T.nz = grid->nz;
     T.ntot = ntot;
-    T.ntx = (grid->nx + taps_tile_x() - 1) / taps_tile_x();
+    T.ntx = (grid->nx + taps_tile_x(fp64[f]) - 1) / taps_tile_x(fp64[f]);
     T.nty = (grid->ny + taps_tile_y() - 1) / taps_tile_y();
     const int R = radii[f];
     for (int m = 0; m < 2 * R + 1; ++m) {
@@ -604,9 +604,18 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     const size_t esize = fp64[f] ? sizeof(double) : sizeof(float);
     const size_t per_plane = 10 * (size_t)plane * esize;
     const int zt = taps_z_planes(fp64[f]);
+    // buffer cap: 8 GiB, raised up to 48 GiB while that leaves half of the free device memory
+    // (with what the context's buffer already holds) to the caller; the slab count does not
+    // change any output, only how many halo planes the x-y pass filters twice
+    size_t cap = kTapBufferCap;
+    {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess)
+        cap = std::max(cap, std::min(kTapBufferMax, (fr + c->xy_cap) / 2));
+    }
     int slab = grid->nz;
-    if (per_plane * (size_t)grid->nz > kTapBufferCap) {
-      slab = (int)(kTapBufferCap / per_plane) - 2 * R;
+    if (per_plane * (size_t)grid->nz > cap) {
+      slab = (int)(cap / per_plane) - 2 * R;
       slab = std::max(zt, slab / zt * zt);
       if (slab + 2 * R >= grid->nz) slab = grid->nz;
     }

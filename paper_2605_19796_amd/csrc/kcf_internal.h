@@ -67,7 +67,7 @@ struct TapArgs {           // general-tap filter (kcf_taps.hip)
   const float* u;
   int nx, ny, nz;
   int64_t ntot;
-  int ntx, nty;            // 16x16 tiles of the x-y pass
+  int ntx, nty;            // tiles of the x-y pass (taps_tile_x, taps_tile_y)
   int zb, nbuf;            // slab buffer: planes zb .. zb + nbuf - 1 (mod nz)
   int zo0, zo1;            // output planes of the z pass
   void* xy;                // slab buffer [10][nbuf][ny][nx], float or double
@@ -104,7 +104,8 @@ hipError_t launch_stream_probe(const float* in, int nin, float* out, int nout, i
 
 // general-tap kernels (kcf_taps.hip)
 constexpr size_t kTapBufferCap = (size_t)8 << 30;  // bytes of x-y filtered planes held at once
-int taps_tile_x();
+constexpr size_t kTapBufferMax = (size_t)48 << 30;  // the same for filter_favre, memory permitting
+int taps_tile_x(int fp64);
 int taps_tile_y();
 int taps_z_planes(int fp64);
 hipError_t launch_taps(const TapArgs& a, int R, int fp64, hipStream_t s);
