@@ -22,6 +22,10 @@ ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++20", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in ordinary vector registers, not accumulation registers: the
+    # learned closure applies its activation to every result, and each result moved out of
+    # an accumulation register costs one more vector instruction
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-result",
     "-Wno-unused-value",
 ]

@@ -18,8 +18,8 @@
 //     the factors of the x and y passes are divided out with it;
 //   * epilogue A: Favre velocity and tau from the FP64 window sums, stored (tall tiles: at
 //     the end of the step), the velocity and rho_bar, tau kept in LDS rings;
-//   * epilogue B: gradient, closures and FP64 statistics of a plane one (short tiles) or two
-//     (tall tiles) planes behind, from the rings.
+//   * epilogue B: gradient, closures and statistics of a plane one (short tiles) or two (tall
+//     tiles) planes behind, from the rings.
 // T is the type of the products and of the x-y passes: double for narrow widths, where tau
 // is a small difference of large filtered products, float otherwise. Outputs are float32.
 #include <type_traits>
@@ -218,9 +218,17 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   double B[10];  // boxcar sums of the 2R planes za - 2R + 1 .. za
 #pragma unroll
   for (int q = 0; q < 10; ++q) B[q] = 0.0;
-  // tall tiles run at two waves per SIMD and keep all 40 sums per lane
-  typename std::conditional<(kBT >= 512), StatLane, StatAcc>::type acc;
-  stat_zero(acc);
+  // Statistics. With FP64 filter sums (narrow widths) every contribution is exact in double
+  // and folded over the wave per point (ten FP64 sums per lane, which keeps these kernels
+  // within the registers of three waves per SIMD); with float32 sums they are summed in
+  // float32 per lane and folded into FP64 every kStatFlush points.
+  constexpr bool kExact = sizeof(T) == 8;
+  StatAcc xacc;      // exact path: the lane's ten 4-lane FP64 sums
+  stat_zero(xacc);
+  StatPart part;     // float32 path: statistics of the points since the last flush
+  stat_zero(part);
+  double acc = 0.0;  // float32 path: this lane's slot of the wave's FP64 record
+  int npart = 0;     // float32 path: points in part (the same in every lane of a wave)
   const bool need_grad = needs_gradient(W);
 
   for (int k = 0; k < nsteps; ++k) {
@@ -396,7 +404,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         P.G[i][2] = (su[(sp * 3 + i) * kBN + ecol] - su[(sm * 3 + i) * kBN + ecol]) * A.inv2h;
         u[i] = ui[ecol];
       }
-      point_closures(W, rb, tau, P);
+      point_closures(W, rb, tau, P, kExact);
       if (valid) {
         const int64_t zb = (int64_t)zg * plane;
         uint32_t o = (uint32_t)(egy * A.nx + egx) * 4u;
@@ -404,22 +412,45 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         store_point_at(W, P, [&](float* b, int c) { return plane_addr(b, c, ntot, zb, o); });
       }
       if (W.partials) {  // uniform
-        StatIn I;
-        stat_inputs(rb, u, tau, P, valid, I);
-        stat_add(I, acc);
+        if constexpr (kExact) {
+          StatIn I;
+          stat_inputs(rb, u, tau, P, valid, I);
+          stat_add(I, xacc);
+        } else {
+          stat_point(rb, u, tau, P.G, P.tgm, smag_dissipation(W, rb, P.G), valid, part);
+          if (++npart == kStatFlush) {  // uniform
+            stat_flush(part, acc);
+            npart = 0;
+          }
+        }
       }
     }
     if (kSplit) store_fields(st_do, st_rb, st_u, st_tau);
   }
-  if (W.partials) write_stats(W.partials + ((int64_t)item * (kBT / 64) + (tid >> 6)) * kNStat, acc);
+  if (W.partials) {
+    double* rec = W.partials + ((int64_t)item * (kBT / 64) + (tid >> 6)) * kNStat;
+    if constexpr (kExact) {
+      write_stats(rec, xacc);
+    } else {
+      if (npart > 0) stat_flush(part, acc);  // uniform
+      write_stat_record(rec, acc);
+    }
+  }
 }
 
 // kOut: which optional gradient-epilogue outputs the call can store (0: none, 1: the gradient
 // and Q only, 2: any); the others, their stores and (below 2) the KC scalars compile away,
 // which also keeps the kernel's scalar registers from spilling
+// The all-outputs level of the float32 8h kernel needs more than the 168 registers of three
+// waves per SIMD (its float32 statistics sums beside every closure output); it runs at two.
+template <int R, typename T, int kOut>
+constexpr int box_waves_out() {
+  return kOut == 2 && R == 4 && sizeof(T) == 4 ? 2 : box_waves<R, T>();
+}
+
 template <int R, typename T, int kOut>
 __global__ void __launch_bounds__(TileFor<R>::BT)
-    __attribute__((amdgpu_waves_per_eu(box_waves<R, T>(), box_waves<R, T>())))
+    __attribute__((amdgpu_waves_per_eu(box_waves_out<R, T, kOut>(), box_waves_out<R, T, kOut>())))
     k_box1(FilterArgs A) {
   __shared__ double smem[BoxLds<R, T>::doubles];
   int item;

@@ -31,7 +31,11 @@ struct PointOut {
 
 // Gradient model rho_bar C M2 (G G^T)_ij (gm_form 0) or the transposed contraction
 // (G^T G)_ij (gm_form 1); gm_coef holds C M2.
+// The closures spell out every fused multiply-add and allow no other contraction, so that a
+// point gets the same bits in every kernel instance, whatever the compiler shares between
+// them and the other per-point expressions of that instance.
 __device__ __forceinline__ void gm_closure(const WidthArgs& W, float rb, PointOut& P) {
+#pragma clang fp contract(off)
   const float(&G)[3][3] = P.G;
   float c = W.gm_coef * rb;
   const int ii[6] = {0, 0, 0, 1, 1, 2};
@@ -43,20 +47,21 @@ __device__ __forceinline__ void gm_closure(const WidthArgs& W, float rb, PointOu
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       const int i = ii[s], j = jj[s];
-      P.tgm[s] = c * (G[i][0] * G[j][0] + G[i][1] * G[j][1] + G[i][2] * G[j][2]);
+      P.tgm[s] = c * fmaf(G[i][0], G[j][0], fmaf(G[i][1], G[j][1], G[i][2] * G[j][2]));
     }
   } else {
     __asm__ volatile("");
 #pragma unroll
     for (int s = 0; s < 6; ++s) {
       const int i = ii[s], j = jj[s];
-      P.tgm[s] = c * (G[0][i] * G[0][j] + G[1][i] * G[1][j] + G[2][i] * G[2][j]);
+      P.tgm[s] = c * fmaf(G[0][i], G[0][j], fmaf(G[1][i], G[1][j], G[2][i] * G[2][j]));
     }
   }
 }
 
 // Smagorinsky -2 rho_bar (C_s Delta)^2 |S| S^d; smag_coef holds (C_s Delta)^2.
 __device__ __forceinline__ void smag_closure(const WidthArgs& W, float rb, PointOut& P) {
+#pragma clang fp contract(off)  // as in gm_closure
   const float(&G)[3][3] = P.G;
   const int ii[6] = {0, 0, 0, 1, 1, 2};
   const int jj[6] = {0, 1, 2, 1, 2, 2};
@@ -69,7 +74,7 @@ __device__ __forceinline__ void smag_closure(const WidthArgs& W, float rb, Point
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) ss += S[i][j] * S[i][j];
+    for (int j = 0; j < 3; ++j) ss = fmaf(S[i][j], S[i][j], ss);
   // the hardware square root (within 1 ulp): a correctly rounded one costs about ten more
   // instructions per point, far below the closure's own accuracy
   const float smag = __builtin_amdgcn_sqrtf(2.f * ss);
@@ -84,28 +89,32 @@ __device__ __forceinline__ void smag_closure(const WidthArgs& W, float rb, Point
 
 // Closures of one point from its gradient (in P.G), filtered density and tau. Only what is
 // stored or reduced is evaluated; the rest is left at zero.
+// exact_stats: the statistics take the exact FP64 path (stat_inputs), which contracts the
+// Smagorinsky tensor; the float32 path (stat_point) needs only its dissipation, which
+// smag_dissipation forms without the tensor. Both need the gradient-model tensor.
 __device__ __forceinline__ void point_closures(const WidthArgs& W, float rb, const float (&tau)[6],
-                                               PointOut& P) {
-  const bool stats = W.partials != nullptr;  // the statistics need both closures
+                                               PointOut& P, bool exact_stats = false) {
+  const bool stats = W.partials != nullptr;
 #pragma unroll
   for (int s = 0; s < 6; ++s) P.tgm[s] = P.tsm[s] = 0.f;
   P.ksgs = P.nut = P.omt = 0.f;
   if (stats || W.tau_gm) {  // uniform
     gm_closure(W, rb, P);
   }
-  if (stats || W.tau_smag) {  // uniform
+  if (W.tau_smag || (stats && exact_stats)) {  // uniform
     smag_closure(W, rb, P);
   }
   if (W.k_sgs || W.nu_t || W.omega_t) {  // uniform; only stored, never reduced
     const float rref = W.ksgs_rho_ref ? 1.f : rb;
     P.ksgs = fabsf(tau[0] + tau[3] + tau[5]) / (2.f * rref);
     P.nut = W.cnu_delta * sqrtf(P.ksgs);
-    P.omt = 1.f / (fmaxf(W.nu_mol, P.nut) * W.inv_theta + W.half_dt);
+    P.omt = 1.f / fmaf(fmaxf(W.nu_mol, P.nut), W.inv_theta, W.half_dt);
   }
 }
 
-// What one point contributes to the FP64 sums. Products of two float32 values are exact in
-// double, so every contribution is formed in double from the stored float outputs. Points
+// What one point contributes to the FP64 sums of the exact path (kernels whose filter sums
+// are FP64). Products of two float32 values are exact in double, so every contribution is
+// formed in double from the stored float outputs. Points
 // outside the interior or with a non-finite value (use false) contribute nothing: the lane
 // fold replaces their inputs by zero before any product is formed, the per-lane sums skip
 // them, so no NaN reaches a sum.
@@ -193,9 +202,96 @@ __device__ __forceinline__ double stat_val(const StatIn& I, int s) {
   return t * g;  // S_TAUTGM
 }
 
-// ---- FP64 statistics: per-point contributions folded over the wave with lane swaps
+// Smagorinsky dissipation -tau^SM_ij S_ij of a point without forming tau^SM: with
+// tau^SM = -2 rho_bar c |S| S^d and S^d : S = S : S - (tr S)^2 / 3 it is
+// 2 rho_bar c |S| (S : S - (tr S)^2 / 3), |S| = sqrt(2 S : S); smag_coef holds c = (C_s Delta)^2.
+__device__ __forceinline__ float smag_dissipation(const WidthArgs& W, float rb,
+                                                  const float (&G)[3][3]) {
+  // no implicit multiply-add contraction: the rounding must not depend on what the compiler
+  // fuses in the surrounding kernel (the statistics of every kernel instance agree bit for bit)
+#pragma clang fp contract(off)
+  const float sxy = 0.5f * (G[0][1] + G[1][0]), sxz = 0.5f * (G[0][2] + G[2][0]);
+  const float syz = 0.5f * (G[1][2] + G[2][1]);
+  const float tr = G[0][0] + G[1][1] + G[2][2];
+  float ss = G[0][0] * G[0][0] + G[1][1] * G[1][1] + G[2][2] * G[2][2];
+  ss = fmaf(2.f * sxy, sxy, fmaf(2.f * sxz, sxz, fmaf(2.f * syz, syz, ss)));
+  const float smag = __builtin_amdgcn_sqrtf(2.f * ss);
+  return 2.f * rb * W.smag_coef * smag * fmaf(-(1.f / 3.f) * tr, tr, ss);
+}
+
+// ---- statistics of the gradient epilogue: float32 sums per lane, FP64 per wave
 //
-// A point's 40 contributions are reduced over the wave in two swap-and-add steps that use
+// A point's 40 contributions (slots of StatSlot) are formed in float32 and added to the
+// thread's float32 partial sums. Every kStatFlush points the partials of the whole wave are
+// folded in a fixed order into one FP64 total per slot, which one lane of the wave adds to
+// its FP64 accumulator; the partials start again from zero. So FP64 is used only where sums
+// run over many points, and a partial holds at most kStatFlush points: its rounding error is
+// below (kStatFlush + 2) 2^-24 times the sum of the magnitudes of its contributions (the
+// products of two float32 values are rounded once, the additions once each). Points that are
+// not used contribute nothing; a point with a non-finite contribution (a NaN or infinite
+// input, or a product beyond the float32 range) is counted in S_NONFINITE and left out.
+constexpr int kStatFlush = 16;
+
+struct StatPart {
+  float s[kNStat];
+};
+
+__device__ __forceinline__ void stat_zero(StatPart& a) {
+#pragma unroll
+  for (int k = 0; k < kNStat; ++k) a.s[k] = 0.f;
+}
+
+// Adds one point: filtered density rb, Favre velocity u, tau and tau^GM (xx xy xz yy yz zz),
+// the gradient G and the Smagorinsky dissipation pism.
+__device__ __forceinline__ void stat_point(float rb, const float (&u)[3], const float (&tau)[6],
+                                           const float (&G)[3][3], const float (&tgm)[6],
+                                           float pism, bool valid, StatPart& a) {
+#pragma clang fp contract(off)  // as in smag_dissipation
+  // S_ij counted for (i, j) and (j, i): G_ii on the diagonal, G_ij + G_ji off it
+  const float m[6] = {G[0][0], G[0][1] + G[1][0], G[0][2] + G[2][0],
+                      G[1][1], G[1][2] + G[2][1], G[2][2]};
+  float pi = 0.f, pigm = 0.f, t2 = 0.f, g2 = 0.f;
+  float tt[6], gg[6], tg[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    pi = fmaf(-tau[s], m[s], pi);
+    pigm = fmaf(-tgm[s], m[s], pigm);
+    tt[s] = tau[s] * tau[s];
+    gg[s] = tgm[s] * tgm[s];
+    tg[s] = tau[s] * tgm[s];
+    t2 += tt[s];
+    g2 += gg[s];
+  }
+  const float ke = 0.5f * rb * fmaf(u[0], u[0], fmaf(u[1], u[1], u[2] * u[2]));
+  // every input reaches one of these through a product, and the squares cover the products
+  // of the correlation sums, so one test on the total covers the point
+  const bool fin = isfinite(pi + pigm + pism + ke + t2 + g2 + pi * pi + pigm * pigm);
+  if (valid && fin) {
+    a.s[S_N] += 1.f;
+    a.s[S_RHO] += rb;
+    a.s[S_KE] += ke;
+    a.s[S_PI] += pi;
+    a.s[S_PIGM] += pigm;
+    a.s[S_PISM] += pism;
+    a.s[S_PI2] = fmaf(pi, pi, a.s[S_PI2]);
+    a.s[S_PIGM2] = fmaf(pigm, pigm, a.s[S_PIGM2]);
+    a.s[S_PIPIGM] = fmaf(pi, pigm, a.s[S_PIPIGM]);
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      a.s[S_TAU + s] += tau[s];
+      a.s[S_TGM + s] += tgm[s];
+      a.s[S_TAU2 + s] += tt[s];
+      a.s[S_TGM2 + s] += gg[s];
+      a.s[S_TAUTGM + s] += tg[s];
+    }
+  } else if (valid) {
+    a.s[S_NONFINITE] += 1.f;
+  }
+}
+
+// ---- FP64 statistics folded over the wave with lane swaps
+//
+// Per-lane values of 40 slots are reduced over the wave in two swap-and-add steps that use
 // the row-swap permutes of gfx950 (lanes L and L ^ 32, then L and L ^ 16): afterwards lane
 // L holds the 4-lane sums of slots 10 * (2 * b5 + b4) + k, k < 10, where b5 and b4 are bits
 // 5 and 4 of L. These ten values are accumulated per lane across every point the thread
@@ -273,32 +369,53 @@ __device__ __forceinline__ void write_stats(double* part, const StatAcc& a) {
   }
 }
 
-// Per-lane sums of all 40 slots, with no lane swaps per point: for kernels whose register
-// budget has room for them (80 registers). The wave reduction at the end applies the same
-// fixed-order fold to the lane sums.
-struct StatLane {
-  double s[kNStat];
-};
-
-__device__ __forceinline__ void stat_zero(StatLane& a) {
-#pragma unroll
-  for (int k = 0; k < kNStat; ++k) a.s[k] = 0.0;
+// Slot whose wave total lane `lane` holds after stat_flush, or -1 (24 lanes hold none).
+__device__ __forceinline__ int stat_lane_slot(int lane) {
+  const int g = 2 * ((lane >> 5) & 1) + ((lane >> 4) & 1);
+  const int base = (lane & 8) ? 5 : 0;
+  const int b2 = (lane >> 2) & 1, b1 = (lane >> 1) & 1, b0 = lane & 1;
+  const int pos = b2 ? (b1 ? -1 : 3 + b0) : (b1 ? (b0 ? -1 : 2) : b0);
+  return pos < 0 ? -1 : 10 * g + base + pos;
 }
 
-__device__ __forceinline__ void stat_add(const StatIn& I, StatLane& a) {
-  if (I.use) {  // lanes of points not used skip the additions
+// Folds the float32 partials of the wave into one FP64 total per slot and adds it to the
+// FP64 accumulator of the lane stat_lane_slot assigns to that slot; clears the partials.
+// The fold: lane swaps across the halves and rows of the wave as in stat_fold (lane L then
+// holds ten 4-lane sums), then within each 16-lane row four exchanges that each halve the
+// values a lane keeps (10 -> 5 -> 3 -> 2 -> 1; a lane that keeps an odd count pads with zero).
+// The order of every addition is fixed. All 64 lanes of the wave must be active.
+__device__ __forceinline__ void stat_flush(StatPart& a, double& acc) {
+  const int lane = __lane_id();
+  double t[10];
 #pragma unroll
-    for (int k = 0; k < kNStat; ++k)
-      if (k != S_NONFINITE) a.s[k] += stat_val(I, k);
+  for (int k = 0; k < 10; ++k) {
+    const double lo = swap_add<32>((double)a.s[k], (double)a.s[k + 20]);
+    const double hi = swap_add<32>((double)a.s[k + 10], (double)a.s[k + 30]);
+    t[k] = swap_add<16>(lo, hi);
   }
-  if (I.bad) a.s[S_NONFINITE] += 1.0;
+  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+  double v5[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const double keep = b3 ? t[i + 5] : t[i];
+    const double send = b3 ? t[i] : t[i + 5];
+    v5[i] = keep + __shfl_xor(send, 8);
+  }
+  double v3[3];
+  v3[0] = (b2 ? v5[3] : v5[0]) + __shfl_xor(b2 ? v5[0] : v5[3], 4);
+  v3[1] = (b2 ? v5[4] : v5[1]) + __shfl_xor(b2 ? v5[1] : v5[4], 4);
+  v3[2] = (b2 ? 0.0 : v5[2]) + __shfl_xor(b2 ? v5[2] : 0.0, 4);
+  double v2[2];
+  v2[0] = (b1 ? v3[2] : v3[0]) + __shfl_xor(b1 ? v3[0] : v3[2], 2);
+  v2[1] = (b1 ? 0.0 : v3[1]) + __shfl_xor(b1 ? v3[1] : 0.0, 2);
+  acc += (b0 ? v2[1] : v2[0]) + __shfl_xor(b0 ? v2[0] : v2[1], 1);
+  stat_zero(a);
 }
 
-__device__ __forceinline__ void write_stats(double* part, const StatLane& a) {
-  StatAcc f;
-  stat_zero(f);
-  stat_fold([&](int s) { return a.s[s]; }, f);
-  write_stats(part, f);
+// The wave's 40-slot record from the lane accumulators of stat_flush.
+__device__ __forceinline__ void write_stat_record(double* part, double acc) {
+  const int slot = stat_lane_slot(__lane_id());
+  if (slot >= 0) part[slot] = acc;
 }
 
 // Whether the gradient epilogue has anything to produce (uniform over the launch).

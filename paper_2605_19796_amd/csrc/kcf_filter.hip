@@ -39,8 +39,9 @@ __global__ void __launch_bounds__(kGX) k_grad_closure(ClosureArgs C) {
     w[i][0] = ui[(int64_t)wrapi(z0 - 1, C.nz) * plane + row + xc];
     w[i][1] = ui[(int64_t)z0 * plane + row + xc];
   }
-  StatAcc acc;
-  stat_zero(acc);
+  static_assert(kGZ <= kStatFlush, "one flush of the statistics per thread");
+  StatPart part;
+  stat_zero(part);
   for (int z = z0; z < z1; ++z) {
     const int64_t base = (int64_t)z * plane;
     const int64_t zpb = (int64_t)(z + 1 == C.nz ? 0 : z + 1) * plane;
@@ -65,9 +66,7 @@ __global__ void __launch_bounds__(kGX) k_grad_closure(ClosureArgs C) {
     point_closures(W, rb, tau, P);
     if (valid) store_point(W, g, C.ntot, P);
     if (W.partials) {  // uniform
-      StatIn I;
-      stat_inputs(rb, u, tau, P, valid, I);
-      stat_add(I, acc);
+      stat_point(rb, u, tau, P.G, P.tgm, smag_dissipation(W, rb, P.G), valid, part);
     }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -77,7 +76,9 @@ __global__ void __launch_bounds__(kGX) k_grad_closure(ClosureArgs C) {
   }
   if (W.partials) {
     const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    write_stats(W.partials + (blk * (kGX / 64) + (threadIdx.x >> 6)) * kNStat, acc);
+    double acc = 0.0;
+    stat_flush(part, acc);
+    write_stat_record(W.partials + (blk * (kGX / 64) + (threadIdx.x >> 6)) * kNStat, acc);
   }
 }
 

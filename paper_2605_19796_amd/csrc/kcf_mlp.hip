@@ -202,6 +202,62 @@ __device__ __forceinline__ void forward(const __bf16* sW, const float* sB, short
   F.y = c;
 }
 
+// Forward pass of NT 16-point tiles at once (inference): every weight operand is read from
+// LDS once and applied to the NT tiles, which also gives the matrix cores NT independent
+// accumulation chains. Per tile the operations and their order are those of forward().
+template <int NT>
+__device__ __forceinline__ void forward_tiles(const __bf16* sW, const float* sB,
+                                              const short4v (&x)[NT], floatx4 (&y)[NT]) {
+  const int lane = __lane_id();
+  const int g = lane >> 4;
+  floatx4 z[NT][4];
+  bf16x8 a[NT][2];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    floatx4 c;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = sB[16 * mt + 4 * g + i];
+    const short4v w = *reinterpret_cast<const short4v*>(sW + (mt * 64 + lane) * 4);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) z[t][mt] = mfma16(w, x[t], c);
+  }
+#pragma unroll
+  for (int l = 1; l <= 3; ++l) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        floatx4 lo, hi;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          lo[i] = gelu(z[t][2 * s][i]);
+          hi[i] = gelu(z[t][2 * s + 1][i]);
+        }
+        a[t][s] = pack8(lo, hi);
+      }
+    }
+    if (l == 3) break;
+    const int base = (l == 1) ? kPF1 : kPF2;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      floatx4 c;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) c[i] = sB[64 * l + 16 * mt + 4 * g + i];
+      const bf16x8 w0 = *reinterpret_cast<const bf16x8*>(sW + base + ((mt * 2) * 64 + lane) * 8);
+      const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(sW + base + ((mt * 2 + 1) * 64 + lane) * 8);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) z[t][mt] = mfma32(w1, a[t][1], mfma32(w0, a[t][0], c));
+    }
+  }
+  floatx4 c;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) c[i] = sB[192 + 4 * g + i];
+  const bf16x8 w0 = *reinterpret_cast<const bf16x8*>(sW + kPF3 + lane * 8);
+  const bf16x8 w1 = *reinterpret_cast<const bf16x8*>(sW + kPF3 + (64 + lane) * 8);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) y[t] = mfma32(w1, a[t][1], mfma32(w0, a[t][0], c));
+}
+
 // ---------------------------------------------------------------- training: forward + backward
 // Each wave handles kTilesPerWave tiles of 16 samples. Writes BF16 activations and deltas
 // feature-major ([feature][batch]) for the weight-gradient GEMM, and per-block FP32 bias
@@ -444,18 +500,35 @@ __device__ __forceinline__ int bias_slot(int i) {
   return -1;
 }
 
+// Gradient of every parameter from the partials of the split-K weight pass and of the
+// forward/backward blocks. A block owns kRedCols consecutive parameters; thread slice k of
+// a column sums partials k, k + kRedSlices, ... and the slices are then added in order, so
+// the result does not depend on timing.
+constexpr int kRedCols = 32, kRedSlices = 8;
+
 __global__ void __launch_bounds__(256) k_grad_reduce(TrainArgs T, int nw_part, int ndb_part,
                                                      float* __restrict__ grad) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kNParams) return;
-  const int bs = bias_slot(i);
+  static_assert(kRedCols * kRedSlices == 256, "one thread per (column, slice)");
+  __shared__ float sp[kRedSlices][kRedCols];
+  const int col = threadIdx.x % kRedCols, slice = threadIdx.x / kRedCols;
+  const int i = blockIdx.x * kRedCols + col;
   float s = 0.f;
-  if (bs < 0) {
-    for (int c = 0; c < nw_part; ++c) s += T.w_part[(int64_t)c * kNParams + i];
-  } else {
-    for (int c = 0; c < ndb_part; ++c) s += T.db_part[(int64_t)c * 198 + bs];
+  if (i < kNParams) {
+    const int bs = bias_slot(i);
+    if (bs < 0) {
+      for (int c = slice; c < nw_part; c += kRedSlices) s += T.w_part[(int64_t)c * kNParams + i];
+    } else {
+      for (int c = slice; c < ndb_part; c += kRedSlices) s += T.db_part[(int64_t)c * 198 + bs];
+    }
   }
-  grad[i] = s;
+  sp[slice][col] = s;
+  __syncthreads();
+  if (slice == 0 && i < kNParams) {
+    float t = sp[0][col];
+#pragma unroll
+    for (int k = 1; k < kRedSlices; ++k) t += sp[k][col];
+    grad[i] = t;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_adam(MlpArgs M, const float* __restrict__ grad,
@@ -650,18 +723,59 @@ __device__ __forceinline__ void wave_lds_sync() {
 constexpr int kXS = 17;  // LDS row stride of one point's 16 standardised inputs (odd: no conflicts)
 constexpr int kYS = 9;   // LDS row stride of one point's outputs
 
+// What the gradient of one point needs: ut_i at the six neighbours (x+, x-, y+, y-, z+, z-)
+// and rho_bar of the point.
+struct InferLoads {
+  float u[3][6];
+  float rb;
+};
+
+// Coordinates of point gi (clamped to the last point past the end) and its loads.
+__device__ __forceinline__ void infer_load(const InferArgs& I, int64_t base, int lane,
+                                           InferLoads& L, int64_t& gc, bool& inside) {
+  const int64_t row = base / I.nx;
+  int x = (int)(base - row * I.nx) + lane;
+  int y = (int)(row % I.ny), z = (int)(row / I.ny);
+  while (x >= I.nx) {
+    x -= I.nx;
+    if (++y == I.ny) {
+      y = 0;
+      ++z;
+    }
+  }
+  const int64_t gi = base + lane;
+  inside = gi < I.ntot;
+  if (!inside) {
+    x = I.nx - 1;
+    y = I.ny - 1;
+    z = I.nz - 1;
+  }
+  gc = inside ? gi : I.ntot - 1;
+  const int64_t plane = (int64_t)I.nx * I.ny;
+  const int64_t o[6] = {gc - x + (x + 1 == I.nx ? 0 : x + 1), gc - x + (x == 0 ? I.nx - 1 : x - 1),
+                        gc + (int64_t)((y + 1 == I.ny ? 0 : y + 1) - y) * I.nx,
+                        gc + (int64_t)((y == 0 ? I.ny - 1 : y - 1) - y) * I.nx,
+                        gc + (int64_t)((z + 1 == I.nz ? 0 : z + 1) - z) * plane,
+                        gc + (int64_t)((z == 0 ? I.nz - 1 : z - 1) - z) * plane};
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int d = 0; d < 6; ++d) L.u[i][d] = I.ut[i * I.ntot + o[d]];
+  L.rb = I.rho_bar[gc];
+}
+
 // One wave per 64 consecutive points. Every lane derives the gradient, the 14 inputs and the
 // envelope test of its own point; the standardised inputs go through LDS into the MFMA
-// layout of four 16-point tiles, and the network outputs come back through LDS to the lane of
-// their point, which applies the unstandardisation, or the gradient model
-// tau_gm = rho_bar C2 G G^T where the inputs leave the training box or are not finite, and
-// stores tau (64 consecutive points per store).
+// layout of four 16-point tiles, which run through the network together, and the network
+// outputs come back through the same LDS rows to the lane of their point, which applies the
+// unstandardisation, or the gradient model tau_gm = rho_bar C2 G G^T where the inputs leave
+// the training box or are not finite, and stores tau (64 consecutive points per store).
 __global__ void __launch_bounds__(256) k_infer(MlpArgs M, InferArgs I) {
   __shared__ __attribute__((aligned(16))) __bf16 sW[kPF3 + 1024];
   __shared__ float sB[208];
   __shared__ float sNorm[68];
   __shared__ float sX[4 * 64 * kXS];
-  __shared__ float sY[4 * 64 * kYS];
+  static_assert(kYS <= kXS, "outputs reuse the input rows");
   stage_params(M, sW, sB, kPF3 + 1024);
   if (threadIdx.x < 14) {
     sNorm[threadIdx.x] = M.x_mu[threadIdx.x];
@@ -677,35 +791,24 @@ __global__ void __launch_bounds__(256) k_infer(MlpArgs M, InferArgs I) {
   const int lane = __lane_id();
   const int g = lane >> 4, p = lane & 15;
   const int wv = threadIdx.x >> 6;
-  float* xw = sX + wv * 64 * kXS;
-  float* yw = sY + wv * 64 * kYS;
+  float* xw = sX + wv * 64 * kXS;  // this wave's 64 rows: inputs, then outputs
   const int64_t ntiles = (I.ntot + 15) / 16;
   const int64_t nchunks = (I.ntot + 63) / 64;
+  const int64_t cstep = (int64_t)gridDim.x * 4;
   int64_t fallback = 0;
   for (int64_t chunk = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + wv); chunk < nchunks;
-       chunk += (int64_t)gridDim.x * 4) {
-    // coordinates of the chunk's first point (uniform), then of this lane's point
-    const int64_t base = chunk * 64;
-    const int64_t row = base / I.nx;
-    int x = (int)(base - row * I.nx) + lane;
-    int y = (int)(row % I.ny), z = (int)(row / I.ny);
-    while (x >= I.nx) {
-      x -= I.nx;
-      if (++y == I.ny) {
-        y = 0;
-        ++z;
-      }
-    }
-    const int64_t gi = base + lane;
-    const bool inside = gi < I.ntot;
-    if (!inside) {
-      x = I.nx - 1;
-      y = I.ny - 1;
-      z = I.nz - 1;
-    }
-    const int64_t gc = inside ? gi : I.ntot - 1;
+       chunk += cstep) {
+    const int64_t gi = chunk * 64 + lane;
+    InferLoads L;
+    int64_t gc;
+    bool in_cur;
+    infer_load(I, chunk * 64, lane, L, gc, in_cur);
+    const float rb = L.rb;
     float G[3][3];
-    grad_at(I.ut, gc, x, y, z, I.nx, I.ny, I.nz, I.ntot, I.inv2h, G);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) G[i][j] = (L.u[i][2 * j] - L.u[i][2 * j + 1]) * I.inv2h;
     float f[14];
     features14(G, I.delta, f);
     bool out = false;
@@ -719,22 +822,28 @@ __global__ void __launch_bounds__(256) k_infer(MlpArgs M, InferArgs I) {
     xr[14] = 0.f;
     xr[15] = 0.f;
     wave_lds_sync();
-#pragma unroll 1
+    // the four tiles through the network together; their outputs go to the rows of their
+    // points after every input row has been read
+    short4v xin[4];
+#pragma unroll
     for (int t = 0; t < 4; ++t) {
       const float* src = xw + (16 * t + p) * kXS + 4 * g;
-      Fwd F;
-      forward(sW, sB, pack4(src[0], src[1], src[2], src[3]), F);
-      float* dst = yw + (16 * t + p) * kYS + 4 * g;
+      xin[t] = pack4(src[0], src[1], src[2], src[3]);
+    }
+    floatx4 yv[4];
+    forward_tiles<4>(sW, sB, xin, yv);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float* dst = xw + (16 * t + p) * kXS + 4 * g;
 #pragma unroll
       for (int i = 0; i < 4; ++i)
-        if (4 * g + i < 6) dst[i] = F.y[i];
+        if (4 * g + i < 6) dst[i] = yv[t][i];
     }
     wave_lds_sync();
-    const float* yr = yw + lane * kYS;
-    const float rb = I.rho_bar[gc];
+    const float* yr = xw + lane * kXS;
     const int ii[6] = {0, 0, 0, 1, 1, 2};
     const int jj[6] = {0, 1, 2, 1, 2, 2};
-    if (inside) {
+    if (in_cur) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         float v;
@@ -747,7 +856,7 @@ __global__ void __launch_bounds__(256) k_infer(MlpArgs M, InferArgs I) {
         I.tau[c * I.ntot + gi] = v;
       }
     }
-    const unsigned long long bal = __ballot(out && inside);
+    const unsigned long long bal = __ballot(out && in_cur);
     if (I.mask && lane < 4 && chunk * 4 + lane < ntiles)
       I.mask[chunk * 4 + lane] = (uint16_t)((bal >> (16 * lane)) & 0xFFFFull);
     fallback += __popcll(bal);
@@ -787,17 +896,19 @@ int fwdbwd_blocks(int batch) {
   return (waves + 3) / 4;
 }
 
+// Samples per block of the split-K weight pass: small enough that a batch of 65 536 spreads
+// over 256 blocks (one per CU), at least one 32-sample K step.
 int wgrad_chunk(int batch) {
   int chunk = 1024;
-  while (chunk > 32 && batch / chunk < 64) chunk /= 2;
+  while (chunk > 32 && batch / chunk < 256) chunk /= 2;
   while (batch % chunk) chunk /= 2;
   return chunk;
 }
 
 hipError_t launch_grad_reduce(const TrainArgs& T, int nw_part, int ndb_part, float* grad,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_grad_reduce, dim3((kNParams + 255) / 256), dim3(256), 0, s, T, nw_part,
-                     ndb_part, grad);
+  hipLaunchKernelGGL(k_grad_reduce, dim3((kNParams + kRedCols - 1) / kRedCols), dim3(256), 0, s,
+                     T, nw_part, ndb_part, grad);
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 // C-ABI layer of the learned closure: parameter state, normalisation, training steps,
 // gradient export, inference over a field, checkpoints.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -28,6 +29,7 @@ struct kcf_mlp {
   float h_norm[68];
   int64_t step = 0;
   int cap = 0;  // batch capacity of the training scratch
+  int nw_cap = 0;  // weight-gradient partials the scratch holds (batch / wgrad_chunk(batch))
   __bf16* d_act = nullptr;
   __bf16* d_dz = nullptr;
   float* d_db_part = nullptr;
@@ -73,8 +75,12 @@ MlpArgs args_of(kcf_mlp* m) {
   return a;
 }
 
+// The split-K pass of a smaller batch can have more partials than that of a larger one (its
+// chunk is the largest power of two dividing the batch), so both capacities are checked.
 int ensure_train(kcf_mlp* m, int batch) {
-  if (batch <= m->cap) return KCF_OK;
+  const int nw_req = batch / wgrad_chunk(batch);
+  if (batch <= m->cap && nw_req <= m->nw_cap) return KCF_OK;
+  batch = std::max(batch, m->cap);
   hipStream_t s = kcf::ctx_stream(m->ctx);
   hipStreamSynchronize(s);
   hipFree(m->d_act);
@@ -85,7 +91,8 @@ int ensure_train(kcf_mlp* m, int batch) {
   m->cap = 0;
   const size_t rows = 16 + 3 * 64;
   const int fb = fwdbwd_blocks(batch);
-  const int nw = batch / wgrad_chunk(batch);
+  const int nw = std::max({nw_req, batch / wgrad_chunk(batch), m->nw_cap});
+  m->nw_cap = 0;
   if (hipMalloc(&m->d_act, rows * batch * sizeof(__bf16)) != hipSuccess ||
       hipMalloc(&m->d_dz, rows * batch * sizeof(__bf16)) != hipSuccess ||
       hipMalloc(&m->d_db_part, (size_t)fb * 198 * sizeof(float)) != hipSuccess ||
@@ -93,6 +100,7 @@ int ensure_train(kcf_mlp* m, int batch) {
       hipMalloc(&m->d_w_part, (size_t)nw * kNParams * sizeof(float)) != hipSuccess)
     return fail(KCF_ENOMEM, "cannot allocate training scratch");
   m->cap = batch;
+  m->nw_cap = nw;
   return KCF_OK;
 }
 

@@ -121,6 +121,28 @@ def test_gradients_match_oracle(ctx, batch):
         assert e <= TOL_GRAD, f"batch {batch}: {name} relative Frobenius error {e:.3e}"
 
 
+def test_grads_smaller_batch_more_partials(ctx):
+    """A batch of 65 504 after one of 65 536 on the same network: its split-K pass has 2 047
+    partials (the chunk is the largest power of two dividing the batch) against 256, so the
+    training scratch must grow although the batch is smaller. Same gradients, bit for bit, as
+    a network that only saw the smaller batch."""
+    say("[gpu] gradient scratch: batch 65504 after 65536")
+    n = 3 * 65536
+    x, y = random_dataset(n, 11)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    rng = np.random.default_rng(12)
+    big = torch.from_numpy(rng.choice(n, 65536, replace=False).astype(np.int32)).cuda()
+    small = torch.from_numpy(rng.choice(n, 65504, replace=False).astype(np.int32)).cuda()
+    m1 = make_mlp(ctx, 5, x, y)
+    m1.grads(xt, yt, big, 65536)
+    l1, g1 = m1.grads(xt, yt, small, 65504)
+    m2 = make_mlp(ctx, 5, x, y)
+    l2, g2 = m2.grads(xt, yt, small, 65504)
+    m1.close()
+    m2.close()
+    assert l1 == l2 and np.array_equal(g1, g2)
+
+
 def test_adam_step(ctx):
     say("[gpu] Adam update")
     x, y = random_dataset(1024, 7)
