@@ -391,7 +391,9 @@ int kcf_mlp_create(kcf_ctx *ctx, kcf_mlp **out);  /* zero parameters, identity n
 void kcf_mlp_destroy(kcf_mlp *mlp);
 int kcf_mlp_set_params(kcf_mlp *mlp, const float *params_host);  /* also resets Adam state */
 int kcf_mlp_get_params(kcf_mlp *mlp, float *params_host);
-int kcf_mlp_set_norm(kcf_mlp *mlp, const float *norm_host);      /* 68 floats, see above */
+/* 68 floats, see above; KCF_EINVAL unless every std is finite and > 0 and every mean finite
+ * (the envelope bounds may be infinite). */
+int kcf_mlp_set_norm(kcf_mlp *mlp, const float *norm_host);
 int kcf_mlp_get_norm(kcf_mlp *mlp, float *norm_host);
 int kcf_mlp_step_count(kcf_mlp *mlp, int64_t *step);
 
@@ -429,7 +431,8 @@ int kcf_mlp_infer_field(kcf_mlp *mlp, const kcf_grid *grid, const float *rho_bar
                         const float *ut, double delta, double m2, float *tau, uint16_t *mask,
                         int64_t *n_fallback);
 /* Checkpoint of parameters, Adam moments, step count and normalisation, with a checksum.
- * Errors: KCF_EIO for unreadable, truncated or corrupted files. */
+ * Errors: KCF_EIO for unreadable, truncated, oversized or corrupted files (the network is
+ * then unchanged), KCF_EINVAL for a checkpoint whose normalisation kcf_mlp_set_norm rejects. */
 int kcf_mlp_save(kcf_mlp *mlp, const char *path);
 int kcf_mlp_load(kcf_mlp *mlp, const char *path);
 

@@ -35,6 +35,9 @@ thread_local std::string g_err;
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
+  // every KCF_ENOMEM follows a failed device allocation, whose error HIP would otherwise
+  // report again at the next launch check of this thread
+  if (code == KCF_ENOMEM) (void)hipGetLastError();
   return code;
 }
 

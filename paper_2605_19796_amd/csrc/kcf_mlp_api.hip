@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "kcf.h"
+#include "kcf_checkpoint.h"
 #include "kcf_internal.h"
 #include "kcf_mlp_internal.h"
 
@@ -45,6 +46,7 @@ struct kcf_mlp {
 namespace {
 
 constexpr int kNormFloats = 68;
+static_assert(kNormFloats == kcf::ckpt::kCkNorm && kNParams == kcf::ckpt::kCkParams, "checkpoint layout");
 constexpr float kB1 = 0.9f, kB2 = 0.999f, kEps = 1e-8f;
 
 int fail(int code, const char* msg) { return kcf::api_fail(code, msg); }
@@ -83,11 +85,12 @@ int ensure_train(kcf_mlp* m, int batch) {
   batch = std::max(batch, m->cap);
   hipStream_t s = kcf::ctx_stream(m->ctx);
   hipStreamSynchronize(s);
-  hipFree(m->d_act);
-  hipFree(m->d_dz);
-  hipFree(m->d_db_part);
-  hipFree(m->d_loss_part);
-  hipFree(m->d_w_part);
+  // freed and cleared together, so that a failed allocation below leaves nothing to free twice
+  for (void** q : {(void**)&m->d_act, (void**)&m->d_dz, (void**)&m->d_db_part,
+                   (void**)&m->d_loss_part, (void**)&m->d_w_part}) {
+    hipFree(*q);
+    *q = nullptr;
+  }
   m->cap = 0;
   const size_t rows = 16 + 3 * 64;
   const int fb = fwdbwd_blocks(batch);
@@ -143,14 +146,6 @@ int forward_backward(kcf_mlp* m, const float* x, const float* y, int64_t n, cons
   return KCF_OK;
 }
 
-uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
-  const unsigned char* b = (const unsigned char*)p;
-  for (size_t i = 0; i < n; ++i) {
-    h ^= b[i];
-    h *= 1099511628211ull;
-  }
-  return h;
-}
 
 }  // namespace
 
@@ -235,12 +230,7 @@ int kcf_mlp_get_params(kcf_mlp* m, float* params) {
 
 int kcf_mlp_set_norm(kcf_mlp* m, const float* norm) {
   if (!m || !norm) return fail(KCF_EINVAL, "NULL argument");
-  for (int i = 0; i < 14; ++i)
-    if (!(norm[14 + i] > 0) || !std::isfinite(norm[i]))
-      return fail(KCF_EINVAL, "input scales must be > 0 and means finite");
-  for (int i = 0; i < 6; ++i)
-    if (!(norm[34 + i] > 0) || !std::isfinite(norm[28 + i]))
-      return fail(KCF_EINVAL, "target scales must be > 0 and means finite");
+  if (const char* why = kcf::ckpt::check_norm(norm)) return fail(KCF_EINVAL, why);
   std::memcpy(m->h_norm, norm, sizeof(m->h_norm));
   hipStream_t s = kcf::ctx_stream(m->ctx);
   MLP_HIP(hipMemcpyAsync(m->d_norm, m->h_norm, sizeof(m->h_norm), hipMemcpyHostToDevice, s),
@@ -449,17 +439,7 @@ int kcf_mlp_save(kcf_mlp* m, const char* path) {
   MLP_HIP(hipMemcpyAsync(buf.data() + kNParams, m->d_m, kNParams * 4, hipMemcpyDeviceToHost, s), "copy");
   MLP_HIP(hipMemcpyAsync(buf.data() + 2 * kNParams, m->d_v, kNParams * 4, hipMemcpyDeviceToHost, s), "copy");
   MLP_HIP(hipStreamSynchronize(s), "sync");
-  std::vector<unsigned char> out;
-  auto put = [&](const void* p, size_t n) {
-    const unsigned char* b = (const unsigned char*)p;
-    out.insert(out.end(), b, b + n);
-  };
-  put("KCFMLP01", 8);
-  put(&m->step, sizeof(m->step));
-  put(buf.data(), buf.size() * 4);
-  put(m->h_norm, sizeof(m->h_norm));
-  const uint64_t h = fnv1a(out.data(), out.size());
-  put(&h, sizeof(h));
+  const std::vector<unsigned char> out = kcf::ckpt::encode(m->step, buf.data(), m->h_norm);
   FILE* f = std::fopen(path, "wb");
   if (!f) return fail(KCF_EIO, "cannot open checkpoint for writing");
   const size_t w = std::fwrite(out.data(), 1, out.size(), f);
@@ -475,22 +455,19 @@ int kcf_mlp_load(kcf_mlp* m, const char* path) {
   std::vector<unsigned char> in;
   unsigned char tmp[65536];
   size_t r;
-  while ((r = std::fread(tmp, 1, sizeof(tmp), f)) > 0) in.insert(in.end(), tmp, tmp + r);
+  // read at most one byte past a checkpoint: enough to tell that a file is too long
+  while (in.size() <= kcf::ckpt::kSize && (r = std::fread(tmp, 1, sizeof(tmp), f)) > 0)
+    in.insert(in.end(), tmp, tmp + r);
   std::fclose(f);
-  const size_t expect = 8 + 8 + 3 * kNParams * 4 + kNormFloats * 4 + 8;
-  if (in.size() != expect) return fail(KCF_EIO, "checkpoint has the wrong size");
-  if (std::memcmp(in.data(), "KCFMLP01", 8) != 0) return fail(KCF_EIO, "not a checkpoint");
-  uint64_t h;
-  std::memcpy(&h, in.data() + expect - 8, 8);
-  if (h != fnv1a(in.data(), expect - 8)) return fail(KCF_EIO, "checkpoint checksum mismatch");
   int64_t step;
-  std::memcpy(&step, in.data() + 8, 8);
-  const float* p = (const float*)(in.data() + 16);
+  std::vector<float> pmv(3 * kNParams);
   float norm[kNormFloats];
-  std::memcpy(norm, in.data() + 16 + 3 * kNParams * 4, sizeof(norm));
+  if (const char* why = kcf::ckpt::decode(in.data(), in.size(), &step, pmv.data(), norm))
+    return fail(KCF_EIO, why);
   int rc = kcf_mlp_set_norm(m, norm);
   if (rc) return rc;
   hipStream_t s = kcf::ctx_stream(m->ctx);
+  const float* p = pmv.data();
   MLP_HIP(hipMemcpyAsync(m->d_params, p, kNParams * 4, hipMemcpyHostToDevice, s), "copy");
   MLP_HIP(hipMemcpyAsync(m->d_m, p + kNParams, kNParams * 4, hipMemcpyHostToDevice, s), "copy");
   MLP_HIP(hipMemcpyAsync(m->d_v, p + 2 * kNParams, kNParams * 4, hipMemcpyHostToDevice, s), "copy");

@@ -143,6 +143,33 @@ def test_grads_smaller_batch_more_partials(ctx):
     assert l1 == l2 and np.array_equal(g1, g2)
 
 
+def test_out_of_memory_reported(ctx):
+    """KCF_ENOMEM: with all but 1 GiB of device memory held by the caller, the training
+    scratch of a batch of 2^22 (3.5 GB) cannot be allocated; the call returns KCF_ENOMEM
+    and the network works as before once the memory is released."""
+    say("[gpu] out-of-memory error path")
+    n = 4096
+    x, y = random_dataset(n, 13)
+    xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    big = 1 << 22
+    idx = torch.from_numpy(np.random.default_rng(14).integers(0, n, big).astype(np.int32)).cuda()
+    m = make_mlp(ctx, 5, x, y)
+    l0, g0 = m.grads(xt, yt, idx[:4096].contiguous(), 4096)
+    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
+    hold = torch.empty(free - (1 << 30), dtype=torch.uint8, device="cuda")
+    try:
+        with pytest.raises(kcf.KcfError) as e:
+            m.grads(xt, yt, idx, big)
+        assert e.value.code == -2, e.value  # KCF_ENOMEM
+    finally:
+        del hold
+        torch.cuda.empty_cache()
+    l1, g1 = m.grads(xt, yt, idx[:4096].contiguous(), 4096)
+    m.close()
+    assert l1 == l0 and np.array_equal(g1, g0)
+
+
 def test_adam_step(ctx):
     say("[gpu] Adam update")
     x, y = random_dataset(1024, 7)
