@@ -7,6 +7,9 @@
         --calls C --points P --workload "..." --fetch DIR --write DIR --calib-fetch DIR \\
         --calib-write DIR --out OUT.json --commands "..." "..."
 
+    python -m paper_2605_19796_amd.profiling sq-counters DIR [DIR ...] --kernel NAME [NAME ...] \
+        --points P --out OUT.txt --commands "..." "..."
+
 kernel-stats: the per-kernel table of a `rocprofv3 --kernel-trace --stats` run (calls, total
 and average duration), as text.
 
@@ -15,6 +18,11 @@ WRITE_SIZE), each scaled by what the same counter reports for a plain device cop
 size (bench.py --copy-calibration), so that the figure does not depend on the counter's unit.
 The summary records the hash of the kernel sources it was taken on; bench.py reports the
 traffic only while that hash matches.
+
+sq-counters: per-dispatch averages of the shader-sequencer counters of the named kernels (one
+`--pmc` run per directory), with instructions per grid point (wave instructions, that is
+per 64 lanes) and the shares of the summed wave lifetime (SQ_WAVE_CYCLES) spent issuing VALU
+and LDS instructions, waiting, and in LDS bank conflicts.
 """
 from __future__ import annotations
 
@@ -134,6 +142,34 @@ def traffic_per_call(args):
     print(json.dumps(res, indent=1))
 
 
+def sq_counters(args):
+    vals = {k: {} for k in args.kernel}
+    for d in args.dirs:
+        for r in csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))):
+            for k in args.kernel:
+                if k in r["Kernel_Name"]:
+                    vals[k].setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    lines = ["# rocprofv3 SQ counters, per-dispatch averages", "# commands:"]
+    lines += [f"#   {c}" for c in args.commands]
+    lines.append(f"# per point: divided by {args.points:.6g} grid points; shares: of SQ_WAVE_CYCLES")
+    for k in args.kernel:
+        a = {c: sum(v) / len(v) for c, v in vals[k].items()}
+        if not a:
+            raise SystemExit(f"no counter rows for {k!r}")
+        lines.append(f"{k}:")
+        for c in sorted(a):
+            per = f"  ({a[c] / args.points:.3f} per point)" if c.startswith("SQ_INSTS") else ""
+            lines.append(f"  {c:24s} {a[c]:16.6g}{per}")
+        wc = a.get("SQ_WAVE_CYCLES")
+        if wc:
+            for c in ("SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT",
+                      "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY"):
+                if c in a:
+                    lines.append(f"  share {c:18s} {a[c] / wc:8.3f}")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -154,8 +190,16 @@ def main():
     c.add_argument("--calls", type=int, required=True)
     c.add_argument("--points", type=float, required=True)
     c.add_argument("--commands", nargs="+", required=True)
+    e = sub.add_parser("sq-counters")
+    e.add_argument("dirs", nargs="+")
+    e.add_argument("--kernel", nargs="+", required=True)
+    e.add_argument("--points", type=float, required=True)
+    e.add_argument("--out", required=True)
+    e.add_argument("--commands", nargs="+", required=True)
     args = ap.parse_args()
-    if args.cmd == "kernel-stats":
+    if args.cmd == "sq-counters":
+        sq_counters(args)
+    elif args.cmd == "kernel-stats":
         kernel_stats(args.dir, args.out, args.command)
     elif args.cmd == "traffic":
         traffic(args)
