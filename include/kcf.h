@@ -93,13 +93,15 @@ typedef struct {
   int ksgs_rho_ref;  /* 0: k_sgs = |tau_kk|/(2 rho_bar) [0]; 1: |tau_kk|/2 (rho0 = 1) */
 } kcf_closure_params;
 
-/* FP64 statistics of one filter width (global reductions on the GPU). Box widths whose filter
- * sums are FP64 form each point's contributions as exact FP64 products of its float32
- * outputs. Box widths with float32 sums (precision 1, or auto above 4h) and every width of the
- * general-tap path (its closure pass) form them in float32 and sum at most 16 points per
- * thread in float32 before the FP64 reduction: a raw sum is then within 25 * 2^-24 of the sum
- * of its terms' magnitudes. A point with a non-finite contribution (a non-finite output, or a
- * float32 product beyond range) is counted in n_nonfinite. */
+/* FP64 statistics of one filter width (global reductions on the GPU). Box widths up to 8h
+ * with precision 2 (FP64 requested explicitly) form each point's contributions as exact FP64
+ * products of its float32 outputs. Every other width (precision 0 or 1, and the general-tap
+ * path's closure pass at any precision) forms them in float32 and sums at most 16 points
+ * (64 contributions: over four lanes per point where the filter sums are FP64, per lane
+ * where they are float32) in float32 before the FP64 reduction: a raw sum is then within
+ * 25 * 2^-24 of the sum of its terms' magnitudes, about the rounding of the float32 outputs
+ * themselves. A point with a non-finite contribution (a non-finite output, or a float32
+ * product beyond range) is counted in n_nonfinite. */
 typedef struct {
   double delta, m2;             /* filter width, second moment of the discrete kernel */
   double mean_rho_bar;          /* <rho_bar> */

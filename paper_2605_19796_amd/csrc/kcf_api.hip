@@ -556,6 +556,7 @@ int kcf_filter_favre(kcf_ctx* c, const kcf_grid* grid, const kcf_filter* filters
     set_outputs(W, &outs[f]);
     set_closure(W, cp, filters[f].delta_over_h * grid->h, taps[f].m2);
     W.partials = stats ? c->d_part + part_off[f] : nullptr;
+    W.exact_stats = filters[f].precision == 2;
   };
   for (int f = 0; f < nf; ++f) {
     if (use_box[f]) {
@@ -705,6 +706,7 @@ int kcf_filter_favre_noalloc(const kcf_grid* grid, const kcf_filter* filters, in
     set_outputs(A[f].wa, &outs[f]);
     set_closure(A[f].wa, cp, filters[f].delta_over_h * grid->h, P.taps[f].m2);
     A[f].wa.partials = d_part;  // every wave writes its record: nothing to clear
+    A[f].wa.exact_stats = filters[f].precision == 2;
     hipError_t e = launch_box(A[f], P.radii[f], P.fp64[f], 8 * A[f].tiles_per_xcd, st);
     if (e != hipSuccess) return hip_fail(e, "box filter launch");
     if (stats) {  // reduce before the next width overwrites the records (same stream)

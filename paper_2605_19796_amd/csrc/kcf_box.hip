@@ -126,9 +126,11 @@ __device__ __forceinline__ void products(const float (&f)[4], T (&p)[10]) {
   p[9] = mz * uz;
 }
 
-template <int R, typename T>
+// kX: exact FP64 statistics contributions (FP64 filter sums only)
+template <int R, typename T, bool kX>
 __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W, int item,
                                          unsigned char* smem) {
+  static_assert(!kX || sizeof(T) == 8, "exact statistics need FP64 filter sums");
   using L = BoxLds<R, T>;
   using C = TileFor<R>;
   constexpr int kBT = C::BT, kBN = C::BN, kBOY = C::BOY, kYP = C::YP, kBYP = C::BYP;
@@ -218,17 +220,24 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   double B[10];  // boxcar sums of the 2R planes za - 2R + 1 .. za
 #pragma unroll
   for (int q = 0; q < 10; ++q) B[q] = 0.0;
-  // Statistics. With FP64 filter sums (narrow widths) every contribution is exact in double
-  // and folded over the wave per point (ten FP64 sums per lane, which keeps these kernels
-  // within the registers of three waves per SIMD); with float32 sums they are summed in
-  // float32 per lane and folded into FP64 every kStatFlush points.
-  constexpr bool kExact = sizeof(T) == 8;
-  StatAcc xacc;      // exact path: the lane's ten 4-lane FP64 sums
+  // Statistics, in one of three forms:
+  //  - exact (kX): every contribution an exact FP64 product, folded over the wave per point
+  //    into ten FP64 sums per lane;
+  //  - FP64 filter sums otherwise: float32 contributions folded over the wave per point into
+  //    ten float32 sums per lane, added to the FP64 ones every kStatFlush points (these
+  //    kernels hold three waves per SIMD, which leaves no room for per-lane sums of all 40
+  //    slots, and the float32 fold takes about 2.5 times fewer instructions than the exact one);
+  //  - float32 filter sums: float32 contributions summed per lane over all 40 slots and folded
+  //    into FP64 every kStatFlush points.
+  constexpr bool kFold = sizeof(T) == 8;  // the first two forms
+  StatAcc xacc;      // wave-fold forms: the lane's ten 4-lane FP64 sums
   stat_zero(xacc);
-  StatPart part;     // float32 path: statistics of the points since the last flush
+  StatFold32 fold;   // float32 fold: the lane's ten 4-lane float32 sums since the last flush
+  stat_zero(fold);
+  StatPart part;     // per-lane form: statistics of the points since the last flush
   stat_zero(part);
-  double acc = 0.0;  // float32 path: this lane's slot of the wave's FP64 record
-  int npart = 0;     // float32 path: points in part (the same in every lane of a wave)
+  double acc = 0.0;  // per-lane form: this lane's slot of the wave's FP64 record
+  int npart = 0;     // points since the last flush (the same in every lane of a wave)
   const bool need_grad = needs_gradient(W);
 
   for (int k = 0; k < nsteps; ++k) {
@@ -404,7 +413,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         P.G[i][2] = (su[(sp * 3 + i) * kBN + ecol] - su[(sm * 3 + i) * kBN + ecol]) * A.inv2h;
         u[i] = ui[ecol];
       }
-      point_closures(W, rb, tau, P, kExact);
+      point_closures(W, rb, tau, P, kX);
       if (valid) {
         const int64_t zb = (int64_t)zg * plane;
         uint32_t o = (uint32_t)(egy * A.nx + egx) * 4u;
@@ -412,10 +421,16 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         store_point_at(W, P, [&](float* b, int c) { return plane_addr(b, c, ntot, zb, o); });
       }
       if (W.partials) {  // uniform
-        if constexpr (kExact) {
+        if constexpr (kX) {
           StatIn I;
           stat_inputs(rb, u, tau, P, valid, I);
           stat_add(I, xacc);
+        } else if constexpr (kFold) {
+          stat_point_fold(rb, u, tau, P.G, P.tgm, smag_dissipation(W, rb, P.G), valid, fold);
+          if (++npart == kStatFlush) {  // uniform
+            stat_flush32(fold, xacc);
+            npart = 0;
+          }
         } else {
           stat_point(rb, u, tau, P.G, P.tgm, smag_dissipation(W, rb, P.G), valid, part);
           if (++npart == kStatFlush) {  // uniform
@@ -429,7 +444,8 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   }
   if (W.partials) {
     double* rec = W.partials + ((int64_t)item * (kBT / 64) + (tid >> 6)) * kNStat;
-    if constexpr (kExact) {
+    if constexpr (kFold) {
+      if (!kX && npart > 0) stat_flush32(fold, xacc);  // uniform
       write_stats(rec, xacc);
     } else {
       if (npart > 0) stat_flush(part, acc);  // uniform
@@ -458,7 +474,19 @@ __global__ void __launch_bounds__(TileFor<R>::BT)
   WidthArgs W = A.wa;
   if constexpr (kOut < 2) W.tau_gm = W.tau_smag = W.k_sgs = W.nu_t = W.omega_t = nullptr;
   if constexpr (kOut < 1) W.grad = W.q_crit = nullptr;
-  box_body<R, T>(A, W, item, reinterpret_cast<unsigned char*>(smem));
+  box_body<R, T, false>(A, W, item, reinterpret_cast<unsigned char*>(smem));
+}
+
+// Exact statistics (FP64 filter sums): one instance per radius, with every output the call
+// may store.
+template <int R>
+__global__ void __launch_bounds__(TileFor<R>::BT)
+    __attribute__((amdgpu_waves_per_eu(box_waves<R, double>(), box_waves<R, double>())))
+    k_box1_exact(FilterArgs A) {
+  __shared__ double smem[BoxLds<R, double>::doubles];
+  int item;
+  if (!map_block(A, item)) return;
+  box_body<R, double, true>(A, A.wa, item, reinterpret_cast<unsigned char*>(smem));
 }
 
 template <int R, typename T>
@@ -470,6 +498,12 @@ BoxGeom geom_of() {
 template <int R, typename T>
 hipError_t launch_of(const FilterArgs& a, int nblocks, hipStream_t s) {
   const WidthArgs& w = a.wa;
+  if constexpr (sizeof(T) == 8) {
+    if (w.partials && w.exact_stats) {
+      hipLaunchKernelGGL((k_box1_exact<R>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
+      return hipGetLastError();
+    }
+  }
   if (w.tau_gm || w.tau_smag || w.k_sgs || w.nu_t || w.omega_t)
     hipLaunchKernelGGL((k_box1<R, T, 2>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
   else if (w.grad || w.q_crit)

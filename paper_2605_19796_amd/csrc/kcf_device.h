@@ -369,6 +369,100 @@ __device__ __forceinline__ void write_stats(double* part, const StatAcc& a) {
   }
 }
 
+// ---- float32 statistics folded over the wave per point (kernels short of registers)
+//
+// The same float32 contributions as stat_point, folded over the wave at every point with the
+// two lane swaps of stat_fold (in float32: one permute and one add per swap), into ten float32
+// sums per lane (lane L then holds 4-lane sums of slots 10 * (2 b5 + b4) + k); every
+// kStatFlush points these are added to the lane's ten FP64 sums (StatAcc) and cleared, and
+// write_stats finishes the reduction once per block. A float32 sum then spans at most
+// 4 kStatFlush contributions: (2 + kStatFlush + 7) 2^-24 of the sum of its terms' magnitudes.
+// Costs 30 registers per lane where stat_point's sums cost 42, and about 2.5 times fewer
+// instructions per point than the exact FP64 fold. All 64 lanes must be active.
+struct StatFold32 {
+  float s[10];
+};
+
+__device__ __forceinline__ void stat_zero(StatFold32& a) {
+#pragma unroll
+  for (int k = 0; k < 10; ++k) a.s[k] = 0.f;
+}
+
+template <int Span>
+__device__ __forceinline__ float swap_add32(float x, float y) {
+  const unsigned xb = __float_as_uint(x), yb = __float_as_uint(y);
+  unsigned nx, ny;
+  if constexpr (Span == 32) {
+    const auto r = __builtin_amdgcn_permlane32_swap(xb, yb, false, false);
+    nx = r[0], ny = r[1];
+  } else {
+    const auto r = __builtin_amdgcn_permlane16_swap(xb, yb, false, false);
+    nx = r[0], ny = r[1];
+  }
+  return __uint_as_float(nx) + __uint_as_float(ny);
+}
+
+__device__ __forceinline__ void stat_point_fold(float rb, const float (&u)[3], const float (&tau)[6],
+                                                const float (&G)[3][3], const float (&tgm)[6],
+                                                float pism, bool valid, StatFold32& a) {
+#pragma clang fp contract(off)  // as in smag_dissipation
+  const float m0[6] = {G[0][0], G[0][1] + G[1][0], G[0][2] + G[2][0],
+                       G[1][1], G[1][2] + G[2][1], G[2][2]};
+  float pi = 0.f, pigm = 0.f, t2 = 0.f, g2 = 0.f;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    pi = fmaf(-tau[s], m0[s], pi);
+    pigm = fmaf(-tgm[s], m0[s], pigm);
+    t2 = fmaf(tau[s], tau[s], t2);
+    g2 = fmaf(tgm[s], tgm[s], g2);
+  }
+  const float ke0 = 0.5f * rb * fmaf(u[0], u[0], fmaf(u[1], u[1], u[2] * u[2]));
+  const bool fin = isfinite(pi + pigm + pism + ke0 + t2 + g2 + pi * pi + pigm * pigm);
+  const bool use = valid && fin;
+  // the inputs of a point that is not used become zero, so that all its sums are zero
+  const float r = use ? rb : 0.f;
+  const float ke = use ? ke0 : 0.f, ps = use ? pism : 0.f, p1 = use ? pi : 0.f;
+  const float p2 = use ? pigm : 0.f;
+  float t[6], g[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    t[s] = use ? tau[s] : 0.f;
+    g[s] = use ? tgm[s] : 0.f;
+  }
+  auto val = [&](int k) -> float {
+    if (k == S_N) return use ? 1.f : 0.f;
+    if (k == S_NONFINITE) return (valid && !fin) ? 1.f : 0.f;
+    if (k == S_RHO) return r;
+    if (k == S_KE) return ke;
+    if (k == S_PI) return p1;
+    if (k == S_PIGM) return p2;
+    if (k == S_PISM) return ps;
+    if (k == S_PI2) return p1 * p1;
+    if (k == S_PIGM2) return p2 * p2;
+    if (k == S_PIPIGM) return p1 * p2;
+    if (k >= S_TAU && k < S_TAU + 6) return t[k - S_TAU];
+    if (k >= S_TGM && k < S_TGM + 6) return g[k - S_TGM];
+    if (k >= S_TAU2 && k < S_TAU2 + 6) return t[k - S_TAU2] * t[k - S_TAU2];
+    if (k >= S_TGM2 && k < S_TGM2 + 6) return g[k - S_TGM2] * g[k - S_TGM2];
+    return t[k - S_TAUTGM] * g[k - S_TAUTGM];  // S_TAUTGM
+  };
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    const float lo = swap_add32<32>(val(k), val(k + 20));
+    const float hi = swap_add32<32>(val(k + 10), val(k + 30));
+    a.s[k] += swap_add32<16>(lo, hi);
+  }
+}
+
+// Adds the ten float32 lane sums to the FP64 ones and clears them.
+__device__ __forceinline__ void stat_flush32(StatFold32& a, StatAcc& acc) {
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    acc.s[k] += (double)a.s[k];
+    a.s[k] = 0.f;
+  }
+}
+
 // Slot whose wave total lane `lane` holds after stat_flush, or -1 (24 lanes hold none).
 __device__ __forceinline__ int stat_lane_slot(int lane) {
   const int g = 2 * ((lane >> 5) & 1) + ((lane >> 4) & 1);

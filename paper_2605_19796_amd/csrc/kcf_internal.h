@@ -36,6 +36,7 @@ struct WidthArgs {          // outputs, closure constants and statistics of one 
   float half_dt;          // dt / 2 of the shifted rate
   int gm_form;            // 0: G G^T, 1: G^T G
   int ksgs_rho_ref;       // 0: rho_bar, 1: 1
+  int exact_stats;        // box kernels with FP64 sums: exact FP64 statistics contributions
   double* partials;       // [records][kNStat] FP64 partial sums (one record per wave), or NULL
 };
 

@@ -2,11 +2,12 @@
 
 Tolerance (floating point): per output component c,
     max_x |gpu_c - oracle_c| / max_x |oracle_c| <= 1e-5
-on the same float32 inputs. Statistics: where the filter sums are FP64 (narrow widths) every
-contribution is exact in double and the GPU's FP64 reductions of its own fields agree with
-host FP64 sums of those fields to 1e-10 relative; where they are float32, contributions and
-per-lane sums of at most 16 points are float32 and agree to 2e-6 of the sum of the terms'
-magnitudes (below); against the oracle's statistics they agree to the field tolerance.
+on the same float32 inputs. Statistics: with FP64 filter sums requested explicitly
+(precision 2) every contribution is exact in double and the GPU's FP64 reductions of its own
+fields agree with host FP64 sums of those fields to 1e-10 relative; otherwise contributions
+and partial sums of at most 64 contributions (16 points) are float32 and agree to 2e-6 of the
+sum of the terms' magnitudes (below); against the oracle's statistics they agree to the field
+tolerance.
 """
 import ctypes as C
 import math
@@ -180,19 +181,19 @@ def test_fields_without_statistics(ctx, kind, nd):
         assert np.array_equal(outs[0][f].cpu().numpy(), full[0][f]), f
 
 
-@pytest.mark.parametrize("nd", [2, 8, 16])
+@pytest.mark.parametrize("nd,prec", [(2, 0), (2, 2), (4, 2), (8, 0), (16, 0)])
 @pytest.mark.parametrize("fields", [("rho_bar", "ut", "tau"), ("rho_bar", "ut", "tau", "grad")])
-def test_statistics_with_fewer_outputs(ctx, nd, fields):
+def test_statistics_with_fewer_outputs(ctx, nd, prec, fields):
     """The calls that store only the Favre fields (the launch the four-width benchmark times),
-    or those and the gradient, run kernels compiled without the other optional outputs; they
-    give the fields and the FP64 sums of the call that stores every output, bit for bit, and
-    the oracle's statistics."""
-    say(f"[gpu] statistics with outputs {fields}, box n={nd}")
+    or those and the gradient, run kernels compiled without the other optional outputs (with
+    exact statistics, one kernel that checks each output); they give the fields and the FP64
+    sums of the call that stores every output, bit for bit, and the oracle's statistics."""
+    say(f"[gpu] statistics with outputs {fields}, box n={nd} precision={prec}")
     rho, u = synth.workload_fields("c512_box_multi", n=40)
     rho, u = rho.numpy(), u.numpy()
     h = 2 * math.pi / 40
-    full, st_full = run_gpu(ctx, rho, u, h, [(F.BOX, nd)])
-    part, st_part = run_gpu(ctx, rho, u, h, [(F.BOX, nd)], fields=fields)
+    full, st_full = run_gpu(ctx, rho, u, h, [(F.BOX, nd, prec)])
+    part, st_part = run_gpu(ctx, rho, u, h, [(F.BOX, nd, prec)], fields=fields)
     for f in fields:
         assert np.array_equal(part[0][f], full[0][f]), f
     assert st_part[0]["raw"] == st_full[0]["raw"]
@@ -238,18 +239,20 @@ def test_galilean_invariance(ctx):
         assert rel(g2[0]["grad"][c], g1[0]["grad"][c]) <= 2e-5
 
 
-def test_float32_statistics_bound(ctx):
-    """Box 8h (float32 filter sums): the statistics are float32 contributions summed per lane
-    over at most 16 points, then FP64. Each point's contribution is formed with at most 7
-    roundings and each lane sum adds at most 16 + 2 more, so every slot lies within
-    (16 + 2 + 7) 2^-24 < 2e-6 of the sum of the magnitudes of its terms from the FP64 host sum
-    of the GPU's own float32 fields; repeated runs agree bit for bit."""
-    say("[gpu] float32 statistics sums against host sums (box 8h, 48^3)")
+@pytest.mark.parametrize("nd", [2, 4, 8])
+def test_float32_statistics_bound(ctx, nd):
+    """Automatic precision: the statistics are float32 contributions, summed in float32 over at
+    most 16 points (box 8h, float32 filter sums: per lane; box 2h and 4h, FP64 filter sums:
+    folded over four lanes per point, then per lane), then FP64. Each point's contribution is
+    formed with at most 7 roundings and each float32 sum adds at most 16 + 2 more, so every
+    slot lies within (16 + 2 + 7) 2^-24 < 2e-6 of the sum of the magnitudes of its terms from
+    the FP64 host sum of the GPU's own float32 fields; repeated runs agree bit for bit."""
+    say(f"[gpu] float32 statistics sums against host sums (box {nd}h, 48^3)")
     rho, u = synth.workload_fields("c256_gauss8", n=48)
     rho, u = rho.numpy(), u.numpy()
     h = 2 * math.pi / 48
-    g1, s1 = run_gpu(ctx, rho, u, h, [(F.BOX, 8)])
-    g2, s2 = run_gpu(ctx, rho, u, h, [(F.BOX, 8)])
+    g1, s1 = run_gpu(ctx, rho, u, h, [(F.BOX, nd)])
+    g2, s2 = run_gpu(ctx, rho, u, h, [(F.BOX, nd)])
     assert s1[0]["raw"] == s2[0]["raw"]
     g = {k: v.astype(np.float64) for k, v in g1[0].items()}
     G = g["grad"].reshape(3, 3, *rho.shape)
@@ -283,15 +286,20 @@ def test_float32_statistics_bound(ctx):
 
 
 def test_determinism_and_reduction_exactness(ctx):
+    """Explicit FP64 (precision 2): exact statistics contributions, FP64 sums within 1e-10 of
+    the host's; the fields are those of the automatic choice (also FP64 sums at 4h), bit for
+    bit."""
     say("[gpu] determinism and FP64 reductions vs host sums")
     rho, u = synth.workload_fields("c256_gauss8", n=48)
     rho, u = rho.numpy(), u.numpy()
     h = 2 * math.pi / 48
-    g1, s1 = run_gpu(ctx, rho, u, h, [(F.BOX, 4)])
-    g2, s2 = run_gpu(ctx, rho, u, h, [(F.BOX, 4)])
+    g1, s1 = run_gpu(ctx, rho, u, h, [(F.BOX, 4, 2)])
+    g2, s2 = run_gpu(ctx, rho, u, h, [(F.BOX, 4, 2)])
+    ga, _ = run_gpu(ctx, rho, u, h, [(F.BOX, 4)])
     assert s1[0]["raw"] == s2[0]["raw"]
     for f in ALL:
         assert np.array_equal(g1[0][f], g2[0][f], equal_nan=True)
+        assert np.array_equal(g1[0][f], ga[0][f], equal_nan=True)
     # host FP64 sums of the GPU's own float32 fields
     g = {k: v.astype(np.float64) for k, v in g1[0].items()}
     G = g["grad"].reshape(3, 3, *rho.shape)
