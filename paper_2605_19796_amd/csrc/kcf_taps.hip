@@ -1,10 +1,12 @@
 // Separable periodic filter with arbitrary symmetric taps w_{-R..R} (the Gaussian kernel, and
 // box widths the sliding-sum kernel does not cover), as two streaming kernels:
 //
-//   k_taps_xy  one workgroup per (tile, plane, group of quantities): the products rho,
-//              rho u_i, rho u_i u_j of the group over the tile and its R-cell halo are staged in
-//              LDS (odd row stride), filtered along both directions and written to a z-slab
-//              buffer [10][planes][ny][nx]. FP32 takes 64x16 tiles and two groups of five
+//   k_taps_xy  one workgroup per (tile, 8 consecutive planes, group of quantities): per
+//              plane the products rho, rho u_i, rho u_i u_j of the group over the tile and its
+//              R-cell halo are staged in LDS (odd row stride), filtered along both directions
+//              and written to a z-slab buffer [10][planes][ny][nx]; the next plane's inputs are
+//              requested right after the staging, so their latency passes under the filter
+//              passes (one plane per workgroup left ~25 % of the kernel waiting on them). FP32 takes 64x16 tiles and two groups of five
 //              quantities, filtered along y first (each task holds one column in registers),
 //              then along x (16-point row segments, back to LDS) and copied out along the
 //              rows: the y pass runs over the halo columns only once per 64 outputs, which
@@ -39,6 +41,7 @@ constexpr int xy_groups() { return sizeof(T) == 8 ? 1 : 2; }
 template <typename T>
 constexpr int xy_threads() { return sizeof(T) == 8 ? 256 : 512; }
 constexpr int kSeg = 16;           // outputs of one x-pass task
+constexpr int kXyPlanes = 8;       // planes of one k_taps_xy workgroup
 constexpr int kZB = 256;           // threads of k_taps_z
 
 template <int R, typename T>
@@ -64,131 +67,164 @@ __global__ void __launch_bounds__(xy_threads<T>()) k_taps_xy(TapArgs A) {
   using L = TapLds<R, T>;
   constexpr int kTX = tile_x<T>(), kTT = xy_threads<T>();
   constexpr int HX = L::HX, HY = L::HY, HXP = L::HXP, QS = L::QS, kQG = L::QG;
+  constexpr int NIT = (L::NRAW + kTT - 1) / kTT;  // staged points per thread
   __shared__ double smem[L::doubles];
   T* buf = reinterpret_cast<T*>(smem);
   const T* w = tap_weights<T>(A);
   const int tid = threadIdx.x;
   const int tile = blockIdx.x;
-  const int p = blockIdx.y;      // buffer plane
+  const int p0 = blockIdx.y * kXyPlanes;  // first buffer plane of this workgroup
+  const int np = min(kXyPlanes, A.nbuf - p0);
   const int grp = blockIdx.z;    // quantities kQG grp .. kQG grp + kQG - 1
   const int tx = tile % A.ntx, ty = tile / A.ntx;
   const int x0 = tx * kTX, y0 = ty * kTY;
   const int64_t plane = (int64_t)A.nx * A.ny;
-  const int64_t zoff = (int64_t)wrapi(A.zb + p, A.nz) * plane;
-  // ---- products of the group, tile and halo
-  for (int r = tid; r < L::NRAW; r += kTT) {
-    const int hx = r % HX, hy = r / HX;
-    const int64_t g = zoff + (int64_t)wrapi(y0 - R + hy, A.ny) * A.nx + wrapi(x0 - R + hx, A.nx);
-    const T rho = (T)A.rho[g];
-    const T ux = (T)A.u[g], uy = (T)A.u[g + A.ntot], uz = (T)A.u[g + 2 * A.ntot];
-    const T mx = rho * ux, my = rho * uy, mz = rho * uz;
-    T* d = buf + hy * HXP + hx;
-    if constexpr (kQG == 10) {
-      d[0] = rho;
-      d[QS] = mx;
-      d[2 * QS] = my;
-      d[3 * QS] = mz;
-      d[4 * QS] = mx * ux;
-      d[5 * QS] = mx * uy;
-      d[6 * QS] = mx * uz;
-      d[7 * QS] = my * uy;
-      d[8 * QS] = my * uz;
-      d[9 * QS] = mz * uz;
-    } else if (grp == 0) {  // uniform
-      d[0] = rho;
-      d[QS] = mx;
-      d[2 * QS] = my;
-      d[3 * QS] = mz;
-      d[4 * QS] = mx * ux;
-    } else {
-      d[0] = mx * uy;
-      d[QS] = mx * uz;
-      d[2 * QS] = my * uy;
-      d[3 * QS] = my * uz;
-      d[4 * QS] = mz * uz;
-    }
-  }
-  __syncthreads();
   const int64_t bplane = (int64_t)A.nbuf * plane;
-  if constexpr (kQG == 10) {
-    // square FP64 tile: x first, in place, one (quantity, row) per task; then y, one
-    // (quantity, column) per task with consecutive lanes on consecutive columns, straight to
-    // the slab buffer
-    for (int t = tid; t < 10 * HY; t += kTT) {
-      T* v = buf + t * HXP;  // row t % HY of quantity t / HY
-      T vr[HX];
+  // in-plane offsets of this thread's staged points (the same on every plane)
+  uint32_t off[NIT];
 #pragma unroll
-      for (int i = 0; i < HX; ++i) vr[i] = v[i];
+  for (int it = 0; it < NIT; ++it) {
+    const int r = min(tid + it * kTT, L::NRAW - 1);
+    const int hx = r % HX, hy = r / HX;
+    off[it] = (uint32_t)(wrapi(y0 - R + hy, A.ny) * A.nx + wrapi(x0 - R + hx, A.nx));
+  }
+  // inputs of the next plane to stage, requested before the passes of the current one
+  float raw[NIT][4];
+  auto fetch = [&](int p) {
+    const int64_t zoff = (int64_t)wrapi(A.zb + p, A.nz) * plane;
+    const float* rz = A.rho + zoff;
+    const float* uz = A.u + zoff;
 #pragma unroll
-      for (int o = 0; o < kTX; ++o) v[o] = tap_sum<R, T>(w, vr, o + R);
-    }
-    __syncthreads();
-    T* out = reinterpret_cast<T*>(A.xy) + (int64_t)p * plane;
-    for (int t = tid; t < 10 * kTX; t += kTT) {
-      const int x = t % kTX, qq = t / kTX;
-      const T* src = buf + qq * QS + x;
-      T vr[HY];
-#pragma unroll
-      for (int i = 0; i < HY; ++i) vr[i] = src[i * HXP];
-      if (x0 + x < A.nx) {
-        T* dst = out + qq * bplane + x0 + x;
-#pragma unroll
-        for (int o = 0; o < kTY; ++o)
-          if (y0 + o < A.ny) dst[(int64_t)(y0 + o) * A.nx] = tap_sum<R, T>(w, vr, o + R);
+    for (int it = 0; it < NIT; ++it) {
+      if (tid + it * kTT < L::NRAW) {
+        raw[it][0] = rz[off[it]];
+        raw[it][1] = uz[off[it]];
+        raw[it][2] = uz[off[it] + A.ntot];
+        raw[it][3] = uz[off[it] + 2 * A.ntot];
       }
     }
-    return;
-  }
-  // ---- y first, in place: one (quantity, column) per task, the tile's rows to rows 0..kTY-1
-  for (int t = tid; t < kQG * HX; t += kTT) {
-    T* col = buf + (t / HX) * QS + t % HX;
-    T vr[HY];
+  };
+  fetch(p0);
+  for (int k = 0; k < np; ++k) {
+    const int p = p0 + k;  // buffer plane
+    if (k > 0) __syncthreads();  // the previous plane's passes are done with the LDS
+    // ---- products of the group, tile and halo
 #pragma unroll
-    for (int i = 0; i < HY; ++i) vr[i] = col[i * HXP];
+    for (int it = 0; it < NIT; ++it) {
+      const int r = tid + it * kTT;
+      if (r >= L::NRAW) continue;
+      const int hx = r % HX, hy = r / HX;
+      const T rho = (T)raw[it][0];
+      const T ux = (T)raw[it][1], uy = (T)raw[it][2], uz = (T)raw[it][3];
+      const T mx = rho * ux, my = rho * uy, mz = rho * uz;
+      T* d = buf + hy * HXP + hx;
+      if constexpr (kQG == 10) {
+        d[0] = rho;
+        d[QS] = mx;
+        d[2 * QS] = my;
+        d[3 * QS] = mz;
+        d[4 * QS] = mx * ux;
+        d[5 * QS] = mx * uy;
+        d[6 * QS] = mx * uz;
+        d[7 * QS] = my * uy;
+        d[8 * QS] = my * uz;
+        d[9 * QS] = mz * uz;
+      } else if (grp == 0) {  // uniform
+        d[0] = rho;
+        d[QS] = mx;
+        d[2 * QS] = my;
+        d[3 * QS] = mz;
+        d[4 * QS] = mx * ux;
+      } else {
+        d[0] = mx * uy;
+        d[QS] = mx * uz;
+        d[2 * QS] = my * uy;
+        d[3 * QS] = my * uz;
+        d[4 * QS] = mz * uz;
+      }
+    }
+    __syncthreads();
+    if (k + 1 < np) fetch(p + 1);
+    if constexpr (kQG == 10) {
+      // square FP64 tile: x first, in place, one (quantity, row) per task; then y, one
+      // (quantity, column) per task with consecutive lanes on consecutive columns, straight to
+      // the slab buffer
+      for (int t = tid; t < 10 * HY; t += kTT) {
+        T* v = buf + t * HXP;  // row t % HY of quantity t / HY
+        T vr[HX];
 #pragma unroll
-    for (int o = 0; o < kTY; ++o) col[o * HXP] = tap_sum<R, T>(w, vr, o + R);
-  }
-  __syncthreads();
-  // ---- x: one (quantity, row, 16-point segment) per thread; the results go back to the
-  // row's first kTX slots once every window is read
-  constexpr int NSEG = kTX / kSeg, NXT = kQG * kTY * NSEG;
-  static_assert(NXT <= kTT, "one x-pass task per thread");
-  const int sg = tid % NSEG, o = (tid / NSEG) % kTY, q = tid / (NSEG * kTY);
-  T res[kSeg];
-  if (tid < NXT) {
-    const T* src = buf + q * QS + o * HXP + sg * kSeg;
-    T vr[kSeg + 2 * R];
+        for (int i = 0; i < HX; ++i) vr[i] = v[i];
 #pragma unroll
-    for (int i = 0; i < kSeg + 2 * R; ++i) vr[i] = src[i];
+        for (int o = 0; o < kTX; ++o) v[o] = tap_sum<R, T>(w, vr, o + R);
+      }
+      __syncthreads();
+      T* out = reinterpret_cast<T*>(A.xy) + (int64_t)p * plane;
+      for (int t = tid; t < 10 * kTX; t += kTT) {
+        const int x = t % kTX, qq = t / kTX;
+        const T* src = buf + qq * QS + x;
+        T vr[HY];
 #pragma unroll
-    for (int j = 0; j < kSeg; ++j) res[j] = tap_sum<R, T>(w, vr, j + R);
-  }
-  __syncthreads();
-  if (tid < NXT) {
-    T* dst = buf + q * QS + o * HXP + sg * kSeg;
+        for (int i = 0; i < HY; ++i) vr[i] = src[i * HXP];
+        if (x0 + x < A.nx) {
+          T* dst = out + qq * bplane + x0 + x;
 #pragma unroll
-    for (int j = 0; j < kSeg; ++j) dst[j] = res[j];
-  }
-  __syncthreads();
-  // ---- copy-out along x: consecutive lanes take consecutive 16-byte pieces of a tile row
-  constexpr int V = 16 / (int)sizeof(T), NV = kTX / V;
-  const bool vec = A.nx % V == 0;  // rows start on 16-byte boundaries
-  T* out = reinterpret_cast<T*>(A.xy) + (int64_t)kQG * grp * bplane + (int64_t)p * plane;
-  for (int e = tid; e < kQG * kTY * NV; e += kTT) {
-    const int xv = e % NV, oo = (e / NV) % kTY, qq = e / (NV * kTY);
-    const int gx = x0 + xv * V, gy = y0 + oo;
-    if (gy >= A.ny || gx >= A.nx) continue;
-    const T* src = buf + qq * QS + oo * HXP + xv * V;
-    T* dst = out + (int64_t)qq * bplane + (int64_t)gy * A.nx + gx;
-    if (vec) {  // gx and nx are multiples of V: the piece lies wholly inside the row
-      if constexpr (sizeof(T) == 4)
-        *reinterpret_cast<float4*>(dst) = make_float4(src[0], src[1], src[2], src[3]);
-      else
-        *reinterpret_cast<double2*>(dst) = make_double2(src[0], src[1]);
-    } else {
+          for (int o = 0; o < kTY; ++o)
+            if (y0 + o < A.ny) dst[(int64_t)(y0 + o) * A.nx] = tap_sum<R, T>(w, vr, o + R);
+        }
+      }
+      continue;
+    }
+    // ---- y first, in place: one (quantity, column) per task, the tile's rows to rows 0..kTY-1
+    for (int t = tid; t < kQG * HX; t += kTT) {
+      T* col = buf + (t / HX) * QS + t % HX;
+      T vr[HY];
 #pragma unroll
-      for (int v = 0; v < V; ++v)
-        if (gx + v < A.nx) dst[v] = src[v];
+      for (int i = 0; i < HY; ++i) vr[i] = col[i * HXP];
+#pragma unroll
+      for (int o = 0; o < kTY; ++o) col[o * HXP] = tap_sum<R, T>(w, vr, o + R);
+    }
+    __syncthreads();
+    // ---- x: one (quantity, row, 16-point segment) per thread; the results go back to the
+    // row's first kTX slots once every window is read
+    constexpr int NSEG = kTX / kSeg, NXT = kQG * kTY * NSEG;
+    static_assert(NXT <= kTT, "one x-pass task per thread");
+    const int sg = tid % NSEG, o = (tid / NSEG) % kTY, q = tid / (NSEG * kTY);
+    T res[kSeg];
+    if (tid < NXT) {
+      const T* src = buf + q * QS + o * HXP + sg * kSeg;
+      T vr[kSeg + 2 * R];
+#pragma unroll
+      for (int i = 0; i < kSeg + 2 * R; ++i) vr[i] = src[i];
+#pragma unroll
+      for (int j = 0; j < kSeg; ++j) res[j] = tap_sum<R, T>(w, vr, j + R);
+    }
+    __syncthreads();
+    if (tid < NXT) {
+      T* dst = buf + q * QS + o * HXP + sg * kSeg;
+#pragma unroll
+      for (int j = 0; j < kSeg; ++j) dst[j] = res[j];
+    }
+    __syncthreads();
+    // ---- copy-out along x: consecutive lanes take consecutive 16-byte pieces of a tile row
+    constexpr int V = 16 / (int)sizeof(T), NV = kTX / V;
+    const bool vec = A.nx % V == 0;  // rows start on 16-byte boundaries
+    T* out = reinterpret_cast<T*>(A.xy) + (int64_t)kQG * grp * bplane + (int64_t)p * plane;
+    for (int e = tid; e < kQG * kTY * NV; e += kTT) {
+      const int xv = e % NV, oo = (e / NV) % kTY, qq = e / (NV * kTY);
+      const int gx = x0 + xv * V, gy = y0 + oo;
+      if (gy >= A.ny || gx >= A.nx) continue;
+      const T* src = buf + qq * QS + oo * HXP + xv * V;
+      T* dst = out + (int64_t)qq * bplane + (int64_t)gy * A.nx + gx;
+      if (vec) {  // gx and nx are multiples of V: the piece lies wholly inside the row
+        if constexpr (sizeof(T) == 4)
+          *reinterpret_cast<float4*>(dst) = make_float4(src[0], src[1], src[2], src[3]);
+        else
+          *reinterpret_cast<double2*>(dst) = make_double2(src[0], src[1]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          if (gx + v < A.nx) dst[v] = src[v];
+      }
     }
   }
 }
@@ -271,7 +307,8 @@ __global__ void __launch_bounds__(kZB) k_taps_z(TapArgs A) {
 
 template <int R, typename T>
 hipError_t launch_taps_of(const TapArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_taps_xy<R, T>), dim3(a.ntx * a.nty, a.nbuf, xy_groups<T>()),
+  hipLaunchKernelGGL((k_taps_xy<R, T>),
+                     dim3(a.ntx * a.nty, (a.nbuf + kXyPlanes - 1) / kXyPlanes, xy_groups<T>()),
                      dim3(xy_threads<T>()), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
