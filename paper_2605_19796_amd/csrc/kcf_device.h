@@ -12,6 +12,17 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// XCD bands for a 1-D grid of 8 * ceil(nitems / 8) workgroups: the hardware hands workgroup L
+// to XCD L % 8, so giving it item (L % 8) * per + L / 8 lets each XCD work through one
+// contiguous range of items, and neighbouring items (which read each other's rows or halos)
+// meet in one L2. False for the padding workgroups past the last item.
+__device__ __forceinline__ bool xcd_band_item(int64_t nitems, int64_t& item) {
+  const int64_t per = (nitems + 7) / 8;
+  const int64_t j = blockIdx.x >> 3;
+  item = (int64_t)(blockIdx.x & 7) * per + j;
+  return j < per && item < nitems;
+}
+
 // sum_m w_m v[c + m], m = -R..R, with w symmetric: w_0 v_c + sum_{m>0} w_m (v_{c+m} + v_{c-m}).
 template <int R, typename T>
 __device__ __forceinline__ T tap_sum(const T* w, const T* v, int c) {

@@ -14,15 +14,19 @@ using namespace dev;
 // Gradient, closures and statistics from stored rho_bar, ut (and tau). A block owns kGX
 // consecutive points of one x-row and kGZ planes; each thread marches along z with the three
 // planes of ut that the z-derivative needs held in registers, and reads its x and y
-// neighbours through the caches. Every lane stays active to the end (the statistics are
-// folded across the full wave).
+// neighbours through the caches (items in XCD bands, x-blocks fastest, then rows: the rows
+// y +- 1 a block reads are those its neighbours in the band load). Every lane stays active
+// to the end (the statistics are folded across the full wave).
 constexpr int kGX = 128, kGZ = 16;
 
 __global__ void __launch_bounds__(kGX) k_grad_closure(ClosureArgs C) {
   const WidthArgs& W = C.wa;
-  const int x = blockIdx.x * kGX + threadIdx.x;
-  const int y = blockIdx.y;
-  const int z0 = blockIdx.z * kGZ;
+  const int nxb = (C.nx + kGX - 1) / kGX;
+  int64_t item;
+  if (!xcd_band_item((int64_t)nxb * C.ny * ((C.nz + kGZ - 1) / kGZ), item)) return;
+  const int x = (int)(item % nxb) * kGX + threadIdx.x;
+  const int y = (int)(item / nxb % C.ny);
+  const int z0 = (int)(item / nxb / C.ny) * kGZ;
   const int z1 = min(z0 + kGZ, C.nz);
   const bool valid = x < C.nx;
   const int xc = valid ? x : 0;
@@ -75,10 +79,9 @@ __global__ void __launch_bounds__(kGX) k_grad_closure(ClosureArgs C) {
     }
   }
   if (W.partials) {
-    const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     double acc = 0.0;
     stat_flush(part, acc);
-    write_stat_record(W.partials + (blk * (kGX / 64) + (threadIdx.x >> 6)) * kNStat, acc);
+    write_stat_record(W.partials + (item * (kGX / 64) + (threadIdx.x >> 6)) * kNStat, acc);
   }
 }
 
@@ -87,7 +90,7 @@ __global__ void __launch_bounds__(kGX) k_grad_closure(ClosureArgs C) {
 // owns kIX consecutive points of one x-row and kIZ planes; each thread marches along z with
 // the seven planes of u_x and u_y that the z-derivatives need held in registers, and reads
 // the x and y neighbours of its plane through the caches, one plane ahead of their use, as
-// a uniform plane base plus 32-bit offsets.
+// a uniform plane base plus 32-bit offsets. Items in XCD bands, x-blocks fastest, then rows.
 constexpr int kIX = 128, kIZ = 16;
 
 __device__ __forceinline__ double d6(float p1, float p2, float p3, float m1, float m2, float m3) {
@@ -96,9 +99,12 @@ __device__ __forceinline__ double d6(float p1, float p2, float p3, float m1, flo
 }
 
 __global__ void __launch_bounds__(kIX) k_input_stats(InputStatArgs S) {
-  const int x = blockIdx.x * kIX + threadIdx.x;
-  const int y = blockIdx.y;
-  const int z0 = blockIdx.z * kIZ;
+  const int nxb = (S.nx + kIX - 1) / kIX;
+  int64_t item;
+  if (!xcd_band_item((int64_t)nxb * S.ny * ((S.nz + kIZ - 1) / kIZ), item)) return;
+  const int x = (int)(item % nxb) * kIX + threadIdx.x;
+  const int y = (int)(item / nxb % S.ny);
+  const int z0 = (int)(item / nxb / S.ny) * kIZ;
   const int z1 = min(z0 + kIZ, S.nz);
   const bool valid = x < S.nx;
   const int xc = valid ? x : 0;
@@ -191,8 +197,7 @@ __global__ void __launch_bounds__(kIX) k_input_stats(InputStatArgs S) {
     a3 += __shfl_xor(a3, d);
   }
   if (__lane_id() == 0) {
-    const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    double* p = S.partials + (blk * (kIX / 64) + (threadIdx.x >> 6)) * 4;
+    double* p = S.partials + (item * (kIX / 64) + (threadIdx.x >> 6)) * 4;
     p[0] = a0;
     p[1] = a1;
     p[2] = a2;
@@ -274,9 +279,13 @@ int64_t grad_closure_records(const ClosureArgs& a) {
   return (int64_t)((a.nx + kGX - 1) / kGX) * a.ny * ((a.nz + kGZ - 1) / kGZ) * (kGX / 64);
 }
 
+// 1-D grids of 8 * ceil(items / 8) workgroups (XCD bands)
+static int64_t banded_blocks(int64_t items) { return 8 * ((items + 7) / 8); }
+
 hipError_t launch_grad_closure(const ClosureArgs& a, hipStream_t s) {
-  const dim3 grid((a.nx + kGX - 1) / kGX, a.ny, (a.nz + kGZ - 1) / kGZ);
-  hipLaunchKernelGGL(k_grad_closure, grid, dim3(kGX), 0, s, a);
+  const int64_t nb = banded_blocks((int64_t)((a.nx + kGX - 1) / kGX) * a.ny * ((a.nz + kGZ - 1) / kGZ));
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_grad_closure, dim3((unsigned)nb), dim3(kGX), 0, s, a);
   return hipGetLastError();
 }
 
@@ -285,8 +294,9 @@ int64_t input_stats_records(const InputStatArgs& a) {
 }
 
 hipError_t launch_input_stats(const InputStatArgs& a, hipStream_t s) {
-  const dim3 grid((a.nx + kIX - 1) / kIX, a.ny, (a.nz + kIZ - 1) / kIZ);
-  hipLaunchKernelGGL(k_input_stats, grid, dim3(kIX), 0, s, a);
+  const int64_t nb = banded_blocks((int64_t)((a.nx + kIX - 1) / kIX) * a.ny * ((a.nz + kIZ - 1) / kIZ));
+  if (nb > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_input_stats, dim3((unsigned)nb), dim3(kIX), 0, s, a);
   return hipGetLastError();
 }
 

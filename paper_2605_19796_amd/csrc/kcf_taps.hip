@@ -72,10 +72,17 @@ __global__ void __launch_bounds__(xy_threads<T>()) k_taps_xy(TapArgs A) {
   T* buf = reinterpret_cast<T*>(smem);
   const T* w = tap_weights<T>(A);
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x;
-  const int p0 = blockIdx.y * kXyPlanes;  // first buffer plane of this workgroup
+  // items (group fastest, then tile, then run of planes) in XCD bands: both groups of a tile
+  // and its neighbouring tiles run close together on one XCD, whose L2 then serves the
+  // inputs the second group and the overlapping halos read again
+  constexpr int NG = xy_groups<T>();
+  const int ntiles = A.ntx * A.nty;
+  int64_t item;
+  if (!xcd_band_item((int64_t)NG * ntiles * ((A.nbuf + kXyPlanes - 1) / kXyPlanes), item)) return;
+  const int grp = (int)(item % NG);  // quantities kQG grp .. kQG grp + kQG - 1
+  const int tile = (int)(item / NG % ntiles);
+  const int p0 = (int)(item / NG / ntiles) * kXyPlanes;  // first buffer plane of this workgroup
   const int np = min(kXyPlanes, A.nbuf - p0);
-  const int grp = blockIdx.z;    // quantities kQG grp .. kQG grp + kQG - 1
   const int tx = tile % A.ntx, ty = tile / A.ntx;
   const int x0 = tx * kTX, y0 = ty * kTY;
   const int64_t plane = (int64_t)A.nx * A.ny;
@@ -307,8 +314,10 @@ __global__ void __launch_bounds__(kZB) k_taps_z(TapArgs A) {
 
 template <int R, typename T>
 hipError_t launch_taps_of(const TapArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_taps_xy<R, T>),
-                     dim3(a.ntx * a.nty, (a.nbuf + kXyPlanes - 1) / kXyPlanes, xy_groups<T>()),
+  const int64_t xy_items =
+      (int64_t)xy_groups<T>() * a.ntx * a.nty * ((a.nbuf + kXyPlanes - 1) / kXyPlanes);
+  if (8 * ((xy_items + 7) / 8) > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_taps_xy<R, T>), dim3((unsigned)(8 * ((xy_items + 7) / 8))),
                      dim3(xy_threads<T>()), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -327,7 +336,6 @@ int taps_tile_y() { return kTY; }
 int taps_z_planes(int fp64) { return fp64 ? z_planes<double>() : z_planes<float>(); }
 
 hipError_t launch_taps(const TapArgs& a, int R, int fp64, hipStream_t s) {
-  if (a.nbuf > 65535) return hipErrorInvalidValue;  // grid y of the x-y pass
 #define KCF_TAPS(RR)                                                                  \
   case RR:                                                                            \
     return fp64 ? launch_taps_of<RR, double>(a, s) : launch_taps_of<RR, float>(a, s);
