@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the kernels of this library.
 
-    python -m paper_2605_19796_amd.profiling kernel-stats DIR OUT.txt --command "..."
+    python -m paper_2605_19796_amd.profiling kernel-stats DIR OUT.txt --command "..." [--top N]
     python -m paper_2605_19796_amd.profiling traffic --kernel NAME --fetch DIR --write DIR \\
         --calib-fetch DIR --calib-write DIR --out OUT.json --commands "..." "..."
     python -m paper_2605_19796_amd.profiling traffic-per-call --kernel NAME [NAME ...] \\
@@ -11,7 +11,7 @@
         --points P --out OUT.txt --commands "..." "..."
 
 kernel-stats: the per-kernel table of a `rocprofv3 --kernel-trace --stats` run (calls, total
-and average duration), as text.
+and average duration), as text: the N kernels of largest total time (default 15).
 
 traffic: HBM bytes per launch of one kernel from two `rocprofv3 --pmc` runs (FETCH_SIZE, then
 WRITE_SIZE), each scaled by what the same counter reports for a plain device copy of known
@@ -177,6 +177,7 @@ def main():
     a.add_argument("dir")
     a.add_argument("out")
     a.add_argument("--command", required=True)
+    a.add_argument("--top", type=int, default=15)
     b = sub.add_parser("traffic")
     for k in ("kernel", "fetch", "write", "calib_fetch", "calib_write", "out"):
         b.add_argument("--" + k.replace("_", "-"), required=True, dest=k)
@@ -200,7 +201,7 @@ def main():
     if args.cmd == "sq-counters":
         sq_counters(args)
     elif args.cmd == "kernel-stats":
-        kernel_stats(args.dir, args.out, args.command)
+        kernel_stats(args.dir, args.out, args.command, args.top)
     elif args.cmd == "traffic":
         traffic(args)
     else:
