@@ -478,13 +478,27 @@ __device__ __forceinline__ void z_group(const MonoArgs& A, int grp, int zl0, int
   }
 }
 
+// Items of the z kernels: (z-chunk, x-block, row), z-chunks fastest, in XCD bands, so that
+// the chunks of one column block run back to back through one L2, which then serves the 2R
+// window planes neighbouring chunks share and the window the next group of monomials reads
+// again (and, for the KC-MP pass, the neighbouring rows). False past the last item.
+template <int ZT>
+__device__ __forceinline__ bool z_item(const MonoArgs& A, int& x, int& y, int& zl0) {
+  const int nzc = (A.nzs + ZT - 1) / ZT, nxb = (A.nx + kZB - 1) / kZB;
+  int64_t item;
+  if (!xcd_band_item((int64_t)nzc * nxb * A.ny, item)) return false;
+  zl0 = (int)(item % nzc) * ZT;
+  const int64_t rest = item / nzc;
+  x = (int)(rest % nxb) * kZB + threadIdx.x;
+  y = (int)(rest / nxb);
+  return x < A.nx;
+}
+
 template <class S, int R, typename T>
 __device__ __forceinline__ void z_pass(const MonoArgs& A) {
   constexpr int ZT = cz_planes<T>();
-  const int x = blockIdx.x * kZB + threadIdx.x;
-  if (x >= A.nx) return;
-  const int y = blockIdx.y;
-  const int zl0 = blockIdx.z * ZT;  // first plane of the thread, relative to the slab
+  int x, y, zl0;  // zl0: first plane of the thread, relative to the slab
+  if (!z_item<ZT>(A, x, y, zl0)) return;
   const int nk = min(ZT, A.nzs - zl0);
   const int64_t plane = (int64_t)A.nx * A.ny;
   const uint32_t cb = (uint32_t)(y * A.nx + x) * (uint32_t)sizeof(float);
@@ -510,10 +524,8 @@ template <int R, typename T>
 __device__ __forceinline__ void z_pass_kc(const MonoArgs& A) {
   constexpr int ZT = cz_planes<T>();
   constexpr int NJ = ZT + 2 * R;  // window planes z0 - R .. z0 + ZT + R - 1
-  const int x = blockIdx.x * kZB + threadIdx.x;
-  if (x >= A.nx) return;
-  const int y = blockIdx.y;
-  const int zl0 = blockIdx.z * ZT;
+  int x, y, zl0;
+  if (!z_item<ZT>(A, x, y, zl0)) return;
   const int nk = min(ZT, A.nzs - zl0);
   const int64_t plane = (int64_t)A.nx * A.ny;
   const int64_t qstride = plane;
@@ -750,7 +762,9 @@ __global__ void __launch_bounds__(kXT) k_kc_xy(MonoArgs A) {
 template <int R>
 hipError_t launch_z_of(const MonoArgs& a, int set, int fp64, hipStream_t s) {
   const int zt = fp64 ? cz_planes<double>() : cz_planes<float>();
-  const dim3 grid((a.nx + kZB - 1) / kZB, a.ny, (a.nzs + zt - 1) / zt);
+  const int64_t items = (int64_t)((a.nzs + zt - 1) / zt) * ((a.nx + kZB - 1) / kZB) * a.ny;
+  if (8 * ((items + 7) / 8) > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(8 * ((items + 7) / 8)));
   if (set == kSetCarrier) {
     if (fp64)
       hipLaunchKernelGGL((k_carrier_z<R, double>), grid, dim3(kZB), 0, s, a);

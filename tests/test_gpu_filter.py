@@ -113,6 +113,10 @@ CASES = [
     ("support_box16_tall", (17, 17, 17), F.BOX, 16),  # window as wide as the grid
     ("support_box10_tall", (11, 30, 11), F.BOX, 10),
     ("gauss4_40", (40, 36, 33), F.GAUSS, 4),
+    # FP32 general taps with ragged x (no 16-byte rows), y and z (the last x-y workgroup
+    # marches fewer than 8 planes)
+    ("ragged_gauss6_fp32", (27, 22, 29), F.GAUSS, 6),
+    ("ragged_box20_taps", (31, 23, 26), F.BOX, 20),
 ]
 
 
