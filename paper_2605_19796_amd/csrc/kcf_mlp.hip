@@ -535,10 +535,12 @@ __global__ void __launch_bounds__(256) k_adam(MlpArgs M, const float* __restrict
                                               AdamArgs A, const double* __restrict__ loss_part,
                                               int nloss, float* __restrict__ loss_out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0 && loss_out) {
+  if (i < 64 && loss_out) {  // the first wave sums the loss partials in a fixed order
     double s = 0;
-    for (int c = 0; c < nloss; ++c) s += loss_part[c];
-    *loss_out = (float)(s / A.loss_den);
+    for (int c = i; c < nloss; c += 64) s += loss_part[c];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (i == 0) *loss_out = (float)(s / A.loss_den);
   }
   if (i >= kNParams) return;
   const float g = grad[i];
