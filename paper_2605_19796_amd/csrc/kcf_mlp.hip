@@ -295,18 +295,45 @@ __global__ void __launch_bounds__(256) k_fwdbwd(MlpArgs M, TrainArgs T) {
 
   const int tiles_total = B / 16;
   const int wave_global = blockIdx.x * 4 + wave;
+  // the rows of every tile of the wave, then the raw inputs and targets of one tile ahead,
+  // requested before the work on the current tile (the gathers are random reads)
+  int64_t smpv[kTilesPerWave];
+#pragma unroll
+  for (int tt = 0; tt < kTilesPerWave; ++tt) {
+    const int tile = wave_global * kTilesPerWave + tt;
+    const int b = tile * 16 + p;
+    int64_t smp = 0;
+    if (tile < tiles_total) smp = T.idx ? (int64_t)T.idx[b] : (int64_t)b;
+    smpv[tt] = smp < 0 ? 0 : (smp >= T.n_rows ? T.n_rows - 1 : smp);
+  }
+  float xr[4], yr[4];
+  auto fetch = [&](int64_t smp) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int f = 4 * g + j;
+      xr[j] = (f < 14) ? T.x[smp * 14 + f] : 0.f;
+      const int o = 4 * g + j;
+      yr[j] = (o < 6) ? T.y[smp * 6 + o] : 0.f;
+    }
+  };
+  if (wave_global * kTilesPerWave < tiles_total) fetch(smpv[0]);
   for (int tt = 0; tt < kTilesPerWave; ++tt) {
     const int tile = wave_global * kTilesPerWave + tt;
     if (tile >= tiles_total) break;  // uniform per wave
     const int b = tile * 16 + p;
-    int64_t smp = T.idx ? (int64_t)T.idx[b] : (int64_t)b;
-    smp = smp < 0 ? 0 : (smp >= T.n_rows ? T.n_rows - 1 : smp);
+    float xc[4], yc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      xc[j] = xr[j];
+      yc[j] = yr[j];
+    }
+    if (tt + 1 < kTilesPerWave && tile + 1 < tiles_total) fetch(smpv[tt + 1]);
     // inputs: features 4g..4g+3 (14 real), standardised
     float xs[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int f = 4 * g + j;
-      xs[j] = (f < 14) ? (T.x[smp * 14 + f] - sNorm[f]) * sNorm[14 + f] : 0.f;
+      xs[j] = (f < 14) ? (xc[j] - sNorm[f]) * sNorm[14 + f] : 0.f;
     }
     const short4v x = pack4(xs[0], xs[1], xs[2], xs[3]);
     Fwd F;
@@ -318,7 +345,7 @@ __global__ void __launch_bounds__(256) k_fwdbwd(MlpArgs M, TrainArgs T) {
       const int o = 4 * g + i;
       float d = 0.f;
       if (o < 6) {
-        const float t = (T.y[smp * 6 + o] - sNorm[28 + o]) * sNorm[34 + o];
+        const float t = (yc[i] - sNorm[28 + o]) * sNorm[34 + o];
         d = F.y[i] - t;
         loss += (double)d * (double)d;
       }
@@ -457,17 +484,40 @@ __global__ void __launch_bounds__(256) k_wgrad(TrainArgs T, int chunk) {
   floatx4 acc[10];
 #pragma unroll
   for (int k = 0; k < 10; ++k) acc[k] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // operands of the next K step are requested before the products of the current one
+  const __bf16* rowD[10];
+  const __bf16* rowA[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    int layer, mt, nt;
+    pair_info(wave * 10 + k, layer, mt, nt);
+    const __bf16* D = layer == 0 ? T.dz[0] : layer == 1 ? T.dz[1] : layer == 2 ? T.dz[2] : T.dz4;
+    const __bf16* Aprev = layer == 0 ? T.act0 : T.act[layer - 1];
+    rowD[k] = D + (16 * mt + r) * B + 8 * g;
+    rowA[k] = Aprev + (16 * nt + r) * B + 8 * g;
+  }
+  bf16x8 na[10], nb[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) {
+    na[k] = *reinterpret_cast<const bf16x8*>(rowD[k] + p0);
+    nb[k] = *reinterpret_cast<const bf16x8*>(rowA[k] + p0);
+  }
   for (int64_t ks = p0; ks < p0 + chunk; ks += 32) {
+    bf16x8 ca[10], cb[10];
 #pragma unroll
     for (int k = 0; k < 10; ++k) {
-      int layer, mt, nt;
-      pair_info(wave * 10 + k, layer, mt, nt);
-      const __bf16* D = layer == 0 ? T.dz[0] : layer == 1 ? T.dz[1] : layer == 2 ? T.dz[2] : T.dz4;
-      const __bf16* Aprev = layer == 0 ? T.act0 : T.act[layer - 1];
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(D + (16 * mt + r) * B + ks + 8 * g);
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(Aprev + (16 * nt + r) * B + ks + 8 * g);
-      acc[k] = mfma32(a, b, acc[k]);
+      ca[k] = na[k];
+      cb[k] = nb[k];
     }
+    if (ks + 32 < p0 + chunk) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) {
+        na[k] = *reinterpret_cast<const bf16x8*>(rowD[k] + ks + 32);
+        nb[k] = *reinterpret_cast<const bf16x8*>(rowA[k] + ks + 32);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[k] = mfma32(ca[k], cb[k], acc[k]);
   }
   float* out = T.w_part + (int64_t)blockIdx.x * kNParams;
 #pragma unroll
