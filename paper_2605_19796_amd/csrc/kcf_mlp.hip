@@ -565,9 +565,12 @@ __global__ void __launch_bounds__(256) k_grad_reduce(TrainArgs T, int nw_part, i
   float s = 0.f;
   if (i < kNParams) {
     const int bs = bias_slot(i);
+    // unrolled so that several loads are in flight; the additions stay in partial order
     if (bs < 0) {
+#pragma unroll 8
       for (int c = slice; c < nw_part; c += kRedSlices) s += T.w_part[(int64_t)c * kNParams + i];
     } else {
+#pragma unroll 8
       for (int c = slice; c < ndb_part; c += kRedSlices) s += T.db_part[(int64_t)c * 198 + bs];
     }
   }
