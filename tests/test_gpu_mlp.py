@@ -97,7 +97,7 @@ def test_forward_matches_oracle(ctx):
     m.close()
 
 
-@pytest.mark.parametrize("batch", [256, 4096, 65536])
+@pytest.mark.parametrize("batch", [32, 96, 256, 4096, 65536])
 def test_gradients_match_oracle(ctx, batch):
     say(f"[gpu] gradients vs oracle, batch {batch}")
     n = 3 * batch
