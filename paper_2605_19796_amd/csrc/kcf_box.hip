@@ -126,8 +126,9 @@ __device__ __forceinline__ void products(const float (&f)[4], T (&p)[10]) {
   p[9] = mz * uz;
 }
 
-// kX: exact FP64 statistics contributions (FP64 filter sums only)
-template <int R, typename T, bool kX>
+// kX: exact FP64 statistics contributions (FP64 filter sums only). kRingOK: the registers
+// allow the ring of arriving inputs below (not at the all-outputs level, which would spill)
+template <int R, typename T, bool kX, bool kRingOK>
 __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W, int item,
                                          unsigned char* smem) {
   static_assert(!kX || sizeof(T) == 8, "exact statistics need FP64 filter sums");
@@ -186,6 +187,11 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   // groups i0 .. i1 - 1; the plane's base addresses are uniform, so each load is a scalar
   // base plus this thread's offset
   float pn[NPF][4], po[NPF][4];
+  // R = 1: the inputs of the last 2R = 2 arriving planes stay in registers (rg[0] the older),
+  // so the plane leaving the window is not read again (wider windows have no registers left
+  // for their 2R planes)
+  constexpr int kRing = R == 1 && kRingOK ? 2 * R : 0;
+  float rg[kRing > 0 ? kRing : 1][NPF][4];
   auto load = [&](float (&pf)[NPF][4], int za, int i0, int i1) {
     const int64_t zoff = (int64_t)wrapi(za, A.nz) * plane;
     const char* b0 = reinterpret_cast<const char*>(A.rho + zoff);
@@ -274,13 +280,28 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
           products<T>(pn[i], d);
           if (leaving) {
             T o[10];
-            products<T>(po[i], o);
+            if constexpr (kRing > 0)
+              products<T>(rg[0][i], o);
+            else
+              products<T>(po[i], o);
 #pragma unroll
             for (int q = 0; q < 10; ++q) d[q] -= o[q];
           }
 #pragma unroll
           for (int q = 0; q < 10; ++q) buf[q * QS + ldoff[i]] = d[q];
         }
+      }
+      if constexpr (kRing > 0) {  // before the next plane's inputs replace pn
+#pragma unroll
+        for (int j = 0; j + 1 < kRing; ++j)
+#pragma unroll
+          for (int i = 0; i < NPF; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) rg[j][i][c] = rg[j + 1][i][c];
+#pragma unroll
+        for (int i = 0; i < NPF; ++i)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) rg[kRing - 1][i][c] = pn[i][c];
       }
       __syncthreads();
       // ---- x pass, in place: one (quantity, row) per task
@@ -379,7 +400,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
         }
       }
     }
-    if (k + 1 < nfilt && k + 1 >= 2 * R) load(po, za + 1 - 2 * R, 0, NPF);
+    if (kRing == 0 && k + 1 < nfilt && k + 1 >= 2 * R) load(po, za + 1 - 2 * R, 0, NPF);
     // Short tiles, every step: the reads of the y-filtered plane are done before the next
     // staging overwrites it, and the velocity of plane zo is in LDS before the gradient
     // reads it. Tall tiles read only planes of earlier steps here, behind the three barriers
@@ -474,7 +495,7 @@ __global__ void __launch_bounds__(TileFor<R>::BT)
   WidthArgs W = A.wa;
   if constexpr (kOut < 2) W.tau_gm = W.tau_smag = W.k_sgs = W.nu_t = W.omega_t = nullptr;
   if constexpr (kOut < 1) W.grad = W.q_crit = nullptr;
-  box_body<R, T, false>(A, W, item, reinterpret_cast<unsigned char*>(smem));
+  box_body<R, T, false, (kOut < 2)>(A, W, item, reinterpret_cast<unsigned char*>(smem));
 }
 
 // Exact statistics (FP64 filter sums): one instance per radius, with every output the call
@@ -486,7 +507,7 @@ __global__ void __launch_bounds__(TileFor<R>::BT)
   __shared__ double smem[BoxLds<R, double>::doubles];
   int item;
   if (!map_block(A, item)) return;
-  box_body<R, double, true>(A, A.wa, item, reinterpret_cast<unsigned char*>(smem));
+  box_body<R, double, true, true>(A, A.wa, item, reinterpret_cast<unsigned char*>(smem));
 }
 
 template <int R, typename T>
