@@ -556,10 +556,11 @@ __device__ __forceinline__ int bias_slot(int i) {
 // the result does not depend on timing.
 constexpr int kRedCols = 32, kRedSlices = 8;
 
-__global__ void __launch_bounds__(256) k_grad_reduce(TrainArgs T, int nw_part, int ndb_part,
-                                                     float* __restrict__ grad) {
+// The gradient of parameter i = blockIdx.x * kRedCols + threadIdx.x % kRedCols, valid in the
+// threads of slice 0 (the others return 0).
+__device__ __forceinline__ float reduce_param(const TrainArgs& T, int nw_part, int ndb_part,
+                                              float (&sp)[kRedSlices][kRedCols]) {
   static_assert(kRedCols * kRedSlices == 256, "one thread per (column, slice)");
-  __shared__ float sp[kRedSlices][kRedCols];
   const int col = threadIdx.x % kRedCols, slice = threadIdx.x / kRedCols;
   const int i = blockIdx.x * kRedCols + col;
   float s = 0.f;
@@ -576,27 +577,25 @@ __global__ void __launch_bounds__(256) k_grad_reduce(TrainArgs T, int nw_part, i
   }
   sp[slice][col] = s;
   __syncthreads();
+  float t = 0.f;
   if (slice == 0 && i < kNParams) {
-    float t = sp[0][col];
+    t = sp[0][col];
 #pragma unroll
     for (int k = 1; k < kRedSlices; ++k) t += sp[k][col];
-    grad[i] = t;
   }
+  return t;
 }
 
-__global__ void __launch_bounds__(256) k_adam(MlpArgs M, const float* __restrict__ grad,
-                                              AdamArgs A, const double* __restrict__ loss_part,
-                                              int nloss, float* __restrict__ loss_out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 64 && loss_out) {  // the first wave sums the loss partials in a fixed order
-    double s = 0;
-    for (int c = i; c < nloss; c += 64) s += loss_part[c];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-    if (i == 0) *loss_out = (float)(s / A.loss_den);
-  }
-  if (i >= kNParams) return;
-  const float g = grad[i];
+__global__ void __launch_bounds__(256) k_grad_reduce(TrainArgs T, int nw_part, int ndb_part,
+                                                     float* __restrict__ grad) {
+  __shared__ float sp[kRedSlices][kRedCols];
+  const float t = reduce_param(T, nw_part, ndb_part, sp);
+  const int i = blockIdx.x * kRedCols + threadIdx.x % kRedCols;
+  if (threadIdx.x < kRedCols && i < kNParams) grad[i] = t;
+}
+
+// Adam update of one parameter from its gradient g (bias-corrected moments, c1 and c2).
+__device__ __forceinline__ void adam_param(const MlpArgs& M, const AdamArgs& A, int i, float g) {
   const float m = A.b1 * M.m[i] + (1.f - A.b1) * g;
   const float v = A.b2 * M.v[i] + (1.f - A.b2) * g * g;
   M.m[i] = m;
@@ -605,6 +604,34 @@ __global__ void __launch_bounds__(256) k_adam(MlpArgs M, const float* __restrict
   const float vh = v * A.c2;  // 1 / (1 - b2^t)
   M.params[i] -= A.lr * mh / (sqrtf(vh) + A.eps);
 }
+
+// Mean loss of the batch from its partials: the first wave of the calling block, in a fixed
+// order.
+__device__ __forceinline__ void loss_mean(const double* __restrict__ loss_part, int nloss,
+                                          double den, float* loss_out) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    double s = 0;
+    for (int c = t; c < nloss; c += 64) s += loss_part[c];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (t == 0) *loss_out = (float)(s / den);
+  }
+}
+
+// The gradient reduction and the Adam step in one launch for a training step: each parameter
+// is updated by the thread that sums its gradient.
+__global__ void __launch_bounds__(256) k_grad_adam(TrainArgs T, int nw_part, int ndb_part,
+                                                   MlpArgs M, AdamArgs A,
+                                                   const double* __restrict__ loss_part, int nloss,
+                                                   float* __restrict__ loss_out) {
+  __shared__ float sp[kRedSlices][kRedCols];
+  const float g = reduce_param(T, nw_part, ndb_part, sp);
+  const int i = blockIdx.x * kRedCols + threadIdx.x % kRedCols;
+  if (threadIdx.x < kRedCols && i < kNParams) adam_param(M, A, i, g);
+  if (blockIdx.x == 0 && loss_out) loss_mean(loss_part, nloss, A.loss_den, loss_out);
+}
+
 
 // ---------------------------------------------------------------- forward on feature rows
 __global__ void __launch_bounds__(256) k_predict(MlpArgs M, const float* __restrict__ x,
@@ -967,12 +994,14 @@ hipError_t launch_grad_reduce(const TrainArgs& T, int nw_part, int ndb_part, flo
   return hipGetLastError();
 }
 
-hipError_t launch_adam(const MlpArgs& M, const float* grad, const AdamArgs& A,
-                       const double* loss_part, int nloss, float* loss_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, M, grad, A, loss_part,
-                     nloss, loss_out);
+hipError_t launch_grad_adam(const TrainArgs& T, int nw_part, int ndb_part, const MlpArgs& M,
+                           const AdamArgs& A, const double* loss_part, int nloss, float* loss_out,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_grad_adam, dim3((kNParams + kRedCols - 1) / kRedCols), dim3(256), 0, s, T,
+                     nw_part, ndb_part, M, A, loss_part, nloss, loss_out);
   return hipGetLastError();
 }
+
 
 hipError_t launch_predict(const MlpArgs& M, const float* x, int64_t n, float* y, hipStream_t s) {
   const int64_t tiles = (n + 15) / 16;

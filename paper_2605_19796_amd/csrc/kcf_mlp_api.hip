@@ -134,15 +134,24 @@ int check_batch(const float* x, const float* y, int64_t n, const int32_t* idx, i
   return KCF_OK;
 }
 
+// Forward/backward and weight-gradient passes; then, with adam NULL, the gradient into
+// m->d_grad, else the gradient reduction and the Adam step (and the loss into loss_dev) in
+// one launch.
 int forward_backward(kcf_mlp* m, const float* x, const float* y, int64_t n, const int32_t* idx,
-                     int batch, int* nfb) {
+                     int batch, int* nfb, const AdamArgs* adam = nullptr,
+                     float* loss_dev = nullptr) {
   int rc = ensure_train(m, batch);
   if (rc) return rc;
   hipStream_t s = kcf::ctx_stream(m->ctx);
   TrainArgs t = train_args(m, x, y, n, idx, batch);
   int nw = 0;
   MLP_HIP(launch_train_passes(args_of(m), t, nfb, &nw, s), "training pass launch");
-  MLP_HIP(launch_grad_reduce(t, nw, *nfb, m->d_grad, s), "gradient reduce launch");
+  if (adam) {
+    MLP_HIP(launch_grad_adam(t, nw, *nfb, args_of(m), *adam, m->d_loss_part, *nfb, loss_dev, s),
+            "gradient and Adam launch");
+  } else {
+    MLP_HIP(launch_grad_reduce(t, nw, *nfb, m->d_grad, s), "gradient reduce launch");
+  }
   return KCF_OK;
 }
 
@@ -352,19 +361,19 @@ int kcf_mlp_train_step(kcf_mlp* m, const float* x, const float* y, int64_t n, co
   int rc = check_batch(x, y, n, idx, batch);
   if (rc) return rc;
   if (!(lr > 0) || !std::isfinite(lr)) return fail(KCF_EINVAL, "learning rate must be > 0");
-  int nfb = 0;
-  if ((rc = forward_backward(m, x, y, n, idx, batch, &nfb))) return rc;
-  m->step += 1;
+  const int64_t step = m->step + 1;
   AdamArgs A;
   A.lr = lr;
   A.b1 = kB1;
   A.b2 = kB2;
   A.eps = kEps;
-  A.c1 = (float)(1.0 / (1.0 - std::pow((double)kB1, (double)m->step)));
-  A.c2 = (float)(1.0 / (1.0 - std::pow((double)kB2, (double)m->step)));
+  A.c1 = (float)(1.0 / (1.0 - std::pow((double)kB1, (double)step)));
+  A.c2 = (float)(1.0 / (1.0 - std::pow((double)kB2, (double)step)));
   A.loss_den = (double)batch * 6.0;
+  int nfb = 0;
+  if ((rc = forward_backward(m, x, y, n, idx, batch, &nfb, &A, loss_dev))) return rc;
+  m->step = step;
   hipStream_t s = kcf::ctx_stream(m->ctx);
-  MLP_HIP(launch_adam(args_of(m), m->d_grad, A, m->d_loss_part, nfb, loss_dev, s), "adam launch");
   MLP_HIP(launch_pack(m->d_params, m->d_packed, s), "pack launch");
   return KCF_OK;
 }
