@@ -193,7 +193,10 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   constexpr int kRing = R == 1 && kRingOK ? 2 * R : 0;
   float rg[kRing > 0 ? kRing : 1][NPF][4];
   auto load = [&](float (&pf)[NPF][4], int za, int i0, int i1) {
-    const int64_t zoff = (int64_t)wrapi(za, A.nz) * plane;
+    // za lies in [z0 - 1 - R, z1 + R] and the grid holds the support (nz >= 2R + 1), so one
+    // period brings it into range (no integer division in the loop)
+    const int zw = za < 0 ? za + A.nz : (za >= A.nz ? za - A.nz : za);
+    const int64_t zoff = (int64_t)zw * plane;
     const char* b0 = reinterpret_cast<const char*>(A.rho + zoff);
     const char* b1 = reinterpret_cast<const char*>(A.u + zoff);
     const char* b2 = reinterpret_cast<const char*>(A.u + ntot + zoff);
