@@ -763,7 +763,7 @@ int kcf_lbm_step(kcf_ctx* c, const kcf_grid* grid, const kcf_lbm_params* p, cons
   A.ntx = (grid->nx + lbm_tile_x() - 1) / lbm_tile_x();
   A.nty = (grid->ny + lbm_tile_y() - 1) / lbm_tile_y();
   A.ntiles = A.ntx * A.nty;
-  A.nzc = choose_zchunks(A.ntiles, grid->nz, 0, 2);
+  A.nzc = choose_zchunks(A.ntiles, grid->nz, 0, 1);  // one 512-thread workgroup per CU
   A.zlen = (grid->nz + A.nzc - 1) / A.nzc;
   A.nzc = (grid->nz + A.zlen - 1) / A.zlen;
   A.items_per_xcd = (A.ntiles * A.nzc + 7) / 8;
