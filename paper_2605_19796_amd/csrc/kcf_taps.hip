@@ -100,14 +100,14 @@ __global__ void __launch_bounds__(xy_threads<T>()) k_taps_xy(TapArgs A) {
   auto fetch = [&](int p) {
     const int64_t zoff = (int64_t)wrapi(A.zb + p, A.nz) * plane;
     const float* rz = A.rho + zoff;
-    const float* uz = A.u + zoff;
+    const float* uv = A.u + zoff;  // u_x of the plane; u_y, u_z follow at ntot strides
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       if (tid + it * kTT < L::NRAW) {
         raw[it][0] = rz[off[it]];
-        raw[it][1] = uz[off[it]];
-        raw[it][2] = uz[off[it] + A.ntot];
-        raw[it][3] = uz[off[it] + 2 * A.ntot];
+        raw[it][1] = uv[off[it]];
+        raw[it][2] = uv[off[it] + A.ntot];
+        raw[it][3] = uv[off[it] + 2 * A.ntot];
       }
     }
   };
