@@ -352,11 +352,14 @@ def test_input_stats(ctx):
         assert abs(st[k] - o[k]) <= 1e-10 * abs(o[k])
 
 
-def test_input_stats_ragged(ctx):
-    """Several z chunks with a short last one, a partial x block and a thin y extent: the
-    neighbour loads fetched one plane ahead stop at the chunk's end and wrap periodically."""
-    say("[gpu] input statistics on a ragged grid")
-    rho, u = synth.random_fields((37, 7, 150), seed=11)
+@pytest.mark.parametrize("shape", [(37, 7, 150), (9, 8, 130), (8, 9, 7)])
+def test_input_stats_ragged(ctx, shape):
+    """Several z chunks with a short last one, a partial x block (of 22 or 2 columns, fewer
+    than the three-point halo) and a thin y extent, and a row as short as the stencil: the
+    neighbour loads fetched one plane ahead stop at the chunk's end, and the LDS row's halo
+    wraps periodically."""
+    say(f"[gpu] input statistics on a ragged grid {shape}")
+    rho, u = synth.random_fields(shape, seed=11)
     st = ctx.input_stats(dev(rho), dev(u), 0.07)
     o = F.input_stats(rho, u, 0.07)
     for k in ("mean_rho", "ek", "enstrophy"):
