@@ -605,6 +605,40 @@ __device__ __forceinline__ void adam_param(const MlpArgs& M, const AdamArgs& A, 
   M.params[i] -= A.lr * mh / (sqrtf(vh) + A.eps);
 }
 
+// The BF16 operand entries of a weight (k_pack's layouts, inverted): after an Adam update
+// the thread that changed parameter i writes them, so a training step needs no packing pass.
+// Biases are not packed. Padding entries never change.
+__device__ __forceinline__ void repack_param(__bf16* __restrict__ out, int i, float v) {
+  const __bf16 b = to_bf16(v);
+  // (s, g, j) of input column c in the 16x16x32 operands: c = perm64(s, g, j)
+  auto inv64 = [](int c, int& sv, int& gv, int& jv) {
+    sv = c >> 5;
+    gv = (c >> 2) & 3;
+    jv = 4 * ((c >> 4) & 1) + (c & 3);
+  };
+  if (i < kOffB1) {  // W1 [64][14]: 16x16x16 [mt][lane][j]
+    const int o = i / 14, in = i % 14;
+    out[((o >> 4) * 64 + 16 * (in >> 2) + (o & 15)) * 4 + (in & 3)] = b;
+  } else if ((i >= kOffW2 && i < kOffB2) || (i >= kOffW3 && i < kOffB3)) {  // W2, W3 [64][64]
+    const bool w2 = i < kOffB2;
+    const int k = i - (w2 ? kOffW2 : kOffW3);
+    const int o = k >> 6, c = k & 63;
+    int sv, gv, jv;
+    inv64(c, sv, gv, jv);  // forward: rows o, K = inputs
+    out[(w2 ? kPF1 : kPF2) + (o >> 4) * 1024 + sv * 512 + (16 * gv + (o & 15)) * 8 + jv] = b;
+    inv64(o, sv, gv, jv);  // transposed: rows = inputs, K = outputs
+    out[(w2 ? kPB1 : kPB2) + (c >> 4) * 1024 + sv * 512 + (16 * gv + (c & 15)) * 8 + jv] = b;
+  } else if (i >= kOffW4 && i < kOffB4) {  // W4 [6][64]
+    const int k = i - kOffW4;
+    const int o = k >> 6, c = k & 63;
+    int sv, gv, jv;
+    inv64(c, sv, gv, jv);  // forward 16x16x32 [s][lane][j], rows = outputs
+    out[kPF3 + sv * 512 + (16 * gv + o) * 8 + jv] = b;
+    // transposed 16x16x16 [mt][lane][j]: rows = inputs, K = outputs
+    out[kPB3 + (c >> 4) * 256 + (16 * (o >> 2) + (c & 15)) * 4 + (o & 3)] = b;
+  }
+}
+
 // Mean loss of the batch from its partials: the first wave of the calling block, in a fixed
 // order.
 __device__ __forceinline__ void loss_mean(const double* __restrict__ loss_part, int nloss,
@@ -624,11 +658,15 @@ __device__ __forceinline__ void loss_mean(const double* __restrict__ loss_part, 
 __global__ void __launch_bounds__(256) k_grad_adam(TrainArgs T, int nw_part, int ndb_part,
                                                    MlpArgs M, AdamArgs A,
                                                    const double* __restrict__ loss_part, int nloss,
-                                                   float* __restrict__ loss_out) {
+                                                   float* __restrict__ loss_out,
+                                                   __bf16* __restrict__ packed) {
   __shared__ float sp[kRedSlices][kRedCols];
   const float g = reduce_param(T, nw_part, ndb_part, sp);
   const int i = blockIdx.x * kRedCols + threadIdx.x % kRedCols;
-  if (threadIdx.x < kRedCols && i < kNParams) adam_param(M, A, i, g);
+  if (threadIdx.x < kRedCols && i < kNParams) {
+    adam_param(M, A, i, g);
+    repack_param(packed, i, M.params[i]);
+  }
   if (blockIdx.x == 0 && loss_out) loss_mean(loss_part, nloss, A.loss_den, loss_out);
 }
 
@@ -996,9 +1034,9 @@ hipError_t launch_grad_reduce(const TrainArgs& T, int nw_part, int ndb_part, flo
 
 hipError_t launch_grad_adam(const TrainArgs& T, int nw_part, int ndb_part, const MlpArgs& M,
                            const AdamArgs& A, const double* loss_part, int nloss, float* loss_out,
-                           hipStream_t s) {
+                           __bf16* packed, hipStream_t s) {
   hipLaunchKernelGGL(k_grad_adam, dim3((kNParams + kRedCols - 1) / kRedCols), dim3(256), 0, s, T,
-                     nw_part, ndb_part, M, A, loss_part, nloss, loss_out);
+                     nw_part, ndb_part, M, A, loss_part, nloss, loss_out, packed);
   return hipGetLastError();
 }
 

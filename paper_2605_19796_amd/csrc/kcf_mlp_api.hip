@@ -147,7 +147,8 @@ int forward_backward(kcf_mlp* m, const float* x, const float* y, int64_t n, cons
   int nw = 0;
   MLP_HIP(launch_train_passes(args_of(m), t, nfb, &nw, s), "training pass launch");
   if (adam) {
-    MLP_HIP(launch_grad_adam(t, nw, *nfb, args_of(m), *adam, m->d_loss_part, *nfb, loss_dev, s),
+    MLP_HIP(launch_grad_adam(t, nw, *nfb, args_of(m), *adam, m->d_loss_part, *nfb, loss_dev,
+                             m->d_packed, s),
             "gradient and Adam launch");
   } else {
     MLP_HIP(launch_grad_reduce(t, nw, *nfb, m->d_grad, s), "gradient reduce launch");
@@ -372,9 +373,7 @@ int kcf_mlp_train_step(kcf_mlp* m, const float* x, const float* y, int64_t n, co
   A.loss_den = (double)batch * 6.0;
   int nfb = 0;
   if ((rc = forward_backward(m, x, y, n, idx, batch, &nfb, &A, loss_dev))) return rc;
-  m->step = step;
-  hipStream_t s = kcf::ctx_stream(m->ctx);
-  MLP_HIP(launch_pack(m->d_params, m->d_packed, s), "pack launch");
+  m->step = step;  // the launch also rewrote the BF16 operands of the updated weights
   return KCF_OK;
 }
 

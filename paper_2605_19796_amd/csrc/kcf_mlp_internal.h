@@ -80,9 +80,11 @@ int fwdbwd_blocks(int batch);
 int wgrad_chunk(int batch);
 hipError_t launch_grad_reduce(const TrainArgs& T, int nw_part, int ndb_part, float* grad,
                               hipStream_t s);
+// The gradient reduction, the Adam step and the BF16 operand entries of the updated weights
+// (packed: the layouts of launch_pack) in one launch.
 hipError_t launch_grad_adam(const TrainArgs& T, int nw_part, int ndb_part, const MlpArgs& M,
                            const AdamArgs& A, const double* loss_part, int nloss, float* loss_out,
-                           hipStream_t s);
+                           __bf16* packed, hipStream_t s);
 hipError_t launch_predict(const MlpArgs& M, const float* x, int64_t n, float* y, hipStream_t s);
 hipError_t launch_features(const FeatArgs& A, hipStream_t s);
 hipError_t launch_colstats(const float* X, int64_t n, int ncol, double* part, int blocks,

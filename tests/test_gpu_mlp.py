@@ -195,6 +195,27 @@ def test_adam_step(ctx):
     m.close()
 
 
+def test_training_step_repacks_operands(ctx):
+    """A training step rewrites the BF16 operand entries of every updated weight in its Adam
+    launch: after a few steps the network predicts exactly what a network packed afresh from
+    the same parameters and normalisation predicts."""
+    say("[gpu] BF16 operands after training steps equal a fresh packing")
+    x, y = random_dataset(4096, 21)
+    X, Y = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    m1 = make_mlp(ctx, 22, x, y)
+    for _ in range(3):
+        m1.train_step(X, Y, None, 2048, 3e-3)
+    torch.cuda.synchronize()
+    m2 = kcf.MLP(ctx)
+    m2.set_params(m1.get_params())
+    m2.set_norm(m1.get_norm())
+    p1 = m1.predict(X[:1024]).cpu().numpy()
+    p2 = m2.predict(X[:1024]).cpu().numpy()
+    m1.close()
+    m2.close()
+    assert np.array_equal(p1, p2)
+
+
 def test_checkpoint_resume(ctx):
     say("[gpu] checkpoint save / load / resume")
     x, y = random_dataset(2048, 9)
