@@ -1,7 +1,7 @@
 """Throughput of the filtering path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-learned]
-                    [--no-carrier] [--no-lbm] [--no-c2]
+                    [--no-carrier] [--no-lbm] [--no-c2] [--oracle-ladder]
 
 Workload: 512^3 periodic grid of synthetic spectral turbulence (u_rms 0.3, k0 16,
 rho = 1 + 0.2 s), FP32 fields resident in HBM; one step = four box-filter widths (2h, 4h,
@@ -23,6 +23,11 @@ Further sections of the same line: `c2`, the 256^3 Gaussian-8h call with the ful
 temperature; `kc_mp`, the a priori KC-MP SGS moment and relaxation-rate field; `lbm`, the D3Q27
 collide-and-stream step of the Taylor-Green vortex with the kinetic closures; `learned`,
 training and the learned-vs-plain race.
+
+`cpu_baseline` times the FP64 oracle on the host cores on a bounded sample of the 512^3 step;
+`oracle_ladder` times it at the configurations' own sizes (full path at 32^3 and 128^3,
+sampled points at 512^3 and 1024^3); --oracle-ladder adds 256^3 and 2^16 sampled points
+(several minutes of CPU work).
 
 Profiling modes (for rocprofv3 runs): --profile-run times a few steps and skips the CPU
 baseline and the learned section; --copy-calibration runs only a plain device copy of known
@@ -120,6 +125,132 @@ def cpu_baseline(rho, u, n_sub=128):
                 sample=f"numpy FP64 oracle, full path at the 4 box widths on one {n_sub}^3 periodic "
                        f"sub-cube of the 512^3 field per process, {nproc} processes of one thread "
                        f"({dt:.1f} s wall, {max(per):.1f} s slowest process)")
+
+
+def _ladder_full_worker(job):
+    """One process of the oracle ladder's full-field mode: the named workload's fields at n^3
+    synthesised on the CPU (untimed), then the oracle's full path at one filter (timed, one
+    thread)."""
+    import time as _t
+    import torch
+    torch.set_num_threads(1)
+    from oracle import fields as F
+    from paper_2605_19796_amd import synth
+    name, n, kind, nd = job
+    r, uu = synth.workload_fields(name, device="cpu", n=n)
+    r, uu = r.double().numpy(), uu.double().numpy()
+    h = 2 * math.pi / n
+    # the steps of the oracle's full path, timed together, with a line after each so that a
+    # long run reports its progress
+    t0 = _t.perf_counter()
+    w, _ = F.filter_weights(kind, nd)
+    rho_bar, ut, tau = F.filter_favre(r, uu, w)
+    t1 = _t.perf_counter()
+    if n >= 256:
+        print(f"[bench] oracle ladder: {n}^3 filter and Favre fields in {t1 - t0:.1f} s",
+              file=sys.stderr, flush=True)
+    G = F.grad2(ut, h)
+    cl = F.closures(rho_bar, G, tau, nd * h, F.second_moment(w, h))
+    F.width_stats(rho_bar, ut, tau, G, cl["tau_gm"])
+    dt = _t.perf_counter() - t0
+    print(f"[bench] oracle ladder: {n}^3 full path done in {dt:.1f} s", file=sys.stderr, flush=True)
+    return dt
+
+
+def _ladder_sampled_worker(job):
+    """One process of the oracle ladder's sampled mode: the oracle's direct 3-D sums at each
+    point, given the point's periodic neighbourhood cube (2R + 3 cells wide, the point at its
+    centre: the sums and the centred gradient then index the cube exactly as they would the
+    whole field)."""
+    import time as _t
+    from oracle import fields as F
+    cubes_r, cubes_u, kind, nd, h = job
+    c = cubes_r.shape[1] // 2
+    t0 = _t.perf_counter()
+    for p in range(cubes_r.shape[0]):
+        F.sampled_points(cubes_r[p], cubes_u[p], kind, nd, h, [(c, c, c)])
+    return _t.perf_counter() - t0
+
+
+def _neighbourhoods(rho, u, R, npts, seed):
+    """npts random points of a periodic field (torch, on the GPU) and their (2R+3)^3 cubes,
+    gathered on the GPU and returned as float32 numpy arrays."""
+    import torch
+    n = rho.shape[0]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    pts = torch.randint(0, n, (npts, 3), generator=g).to(rho.device)
+    offs = torch.arange(-(R + 1), R + 2, device=rho.device)
+    kz = (pts[:, 0, None] + offs) % n
+    jy = (pts[:, 1, None] + offs) % n
+    ix = (pts[:, 2, None] + offs) % n
+    flat = (kz[:, :, None, None] * n + jy[:, None, :, None]) * n + ix[:, None, None, :]
+    cr = rho.reshape(-1)[flat].cpu().numpy()
+    cu = torch.stack([u[a].reshape(-1)[flat] for a in range(3)], dim=1).cpu().numpy()
+    return cr, cu
+
+
+def oracle_ladder(full: bool):
+    """The FP64 oracle timed on the host cores at the configurations' own sizes: the full-field
+    path at 32^3 (box 4h), 128^3 and 256^3 (Gaussian 8h), on one process of one thread and on
+    P processes of one thread each (P = host cores, at most 16), and the sampled-point mode
+    (direct 3-D sums) at 512^3 (box 16h) and 1024^3 (Gaussian 8h) on random points split over
+    P processes. The default run takes 32^3 and 128^3 (the latter on P processes only) and 256
+    sampled points per grid; `full` adds 128^3 alone, 256^3 and 2^16 sampled points."""
+    import multiprocessing as mp
+    import torch
+    from oracle import fields as F
+    from paper_2605_19796_amd import synth
+    nproc = max(1, min(os.cpu_count() or 1, 16))
+    ctx = mp.get_context("spawn")
+    out = []
+    env_old = os.environ.get("OMP_NUM_THREADS")
+    os.environ["OMP_NUM_THREADS"] = "1"  # inherited by the spawned workers
+    try:
+        cases = [("c32_box4", 32, F.BOX, 4), ("c256_gauss8", 128, F.GAUSS, 8)]
+        if full:
+            cases.append(("c256_gauss8", 256, F.GAUSS, 8))
+        with ctx.Pool(nproc) as pool:
+            for name, n, kind, nd in cases:
+                rec = dict(mode="full", grid=n, filter=f"{'box' if kind == F.BOX else 'gauss'} {nd}h")
+                if full or n <= 32:  # one process alone (the default run takes the per-process
+                    progress(f"oracle ladder: {n}^3 full path, 1 process")  # times below)
+                    one = pool.map(_ladder_full_worker, [(name, n, kind, nd)])[0]
+                    rec.update(one_process_s=one, one_process_points_per_s=n ** 3 / one)
+                # the 256^3 path holds ~7 GB per process
+                p = nproc if n <= 128 else min(nproc, 8)
+                progress(f"oracle ladder: {n}^3 full path, {p} processes")
+                t0 = time.perf_counter()
+                per = pool.map(_ladder_full_worker, [(name, n, kind, nd)] * p)
+                wall = time.perf_counter() - t0
+                rec.update(processes=p, wall_s=wall, points_per_s=p * n ** 3 / wall,
+                           slowest_process_s=max(per), fastest_process_s=min(per))
+                out.append(rec)
+            npts = 1 << 16 if full else 256
+            for name, n, kind, nd in [("c512_box_multi", 512, F.BOX, 16),
+                                      ("c1024_learned", 1024, F.GAUSS, 8)]:
+                progress(f"oracle ladder: {n}^3 sampled mode, {npts} points")
+                rho, u = synth.workload_fields(name, device="cuda")
+                R = F.filter_weights(kind, nd)[1]
+                chunk = max(1, npts // (4 * nproc))
+                jobs = []
+                for s in range(0, npts, chunk):
+                    cr, cu = _neighbourhoods(rho, u, R, min(chunk, npts - s), seed=n + s)
+                    jobs.append((cr, cu, kind, nd, 2 * math.pi / n))
+                del rho, u
+                torch.cuda.empty_cache()
+                t0 = time.perf_counter()
+                per = pool.map(_ladder_sampled_worker, jobs)
+                wall = time.perf_counter() - t0
+                out.append(dict(mode="sampled", grid=n, filter=f"{'box' if kind == F.BOX else 'gauss'} "
+                                f"{nd}h", points=npts, processes=nproc, wall_s=wall,
+                                points_per_s=npts / wall,
+                                one_thread_points_per_s=npts / sum(per)))
+    finally:
+        if env_old is None:
+            os.environ.pop("OMP_NUM_THREADS", None)
+        else:
+            os.environ["OMP_NUM_THREADS"] = env_old
+    return dict(kind="oracle", cores=nproc, threads_per_process=1, runs=out)
 
 
 def progress(msg):
@@ -493,7 +624,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU baseline and the oracle ladder")
+    ap.add_argument("--oracle-ladder", action="store_true",
+                    help="the full oracle ladder (256^3 full path, 2^16 sampled points; minutes)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-carrier", action="store_true",
                     help="skip the carrier, third-order moment and KC-MP sections")
@@ -605,6 +739,8 @@ def main():
         line["cpu_baseline"] = cpu_baseline(rho, u)
     del outs
     torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        line["oracle_ladder"] = oracle_ladder(args.oracle_ladder)
     if not args.no_c2:
         line["c2"] = c2_section(ctx, args)
     if not args.no_carrier:
