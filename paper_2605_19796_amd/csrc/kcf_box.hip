@@ -3,11 +3,13 @@
 //
 // A workgroup owns a tile of columns (the output columns plus the one-cell halo of the
 // central-difference gradient) and marches along z: short tiles (18x14 columns, 256 threads,
-// three workgroups per CU) for R <= 4, tall tiles (18x28, 512 threads, one per CU) beyond.
-// At step k the plane za = za0 + k arrives:
-//   * staging: the inputs of plane za and of plane za - 2R (the one leaving the window; it is
-//     read a second time, from cache), loaded during the previous step, are turned into the
-//     differences d = P(za) - P(za - 2R) of the ten products P = rho, rho u_i, rho u_i u_j;
+// three workgroups per CU) for R = 1, R = 3 and FP64 products at R = 4, tall tiles (18x28,
+// 512 threads, one per CU) otherwise. At step k the plane za = za0 + k arrives:
+//   * staging: the inputs of plane za and of plane za - 2R (the one leaving the window: kept
+//     in registers since it arrived where they allow, R = 1 and tall tiles up to R = 4,
+//     otherwise read a second time, from cache), loaded during the previous step, are turned
+//     into the differences d = P(za) - P(za - 2R) of the ten products P = rho, rho u_i,
+//     rho u_i u_j;
 //   * x pass and y pass through LDS: each task slides a trapezoid window over one row
 //     (column) of one quantity in registers, three operations per output (the window is the
 //     sum of two boxcars, unscaled: each pass multiplies by 2n); the y pass works in place in
@@ -38,7 +40,10 @@ constexpr int kLdsPerCU = 160 * 1024;
 
 // Tile and workgroup shape. Narrow windows use short tiles (18x14 columns, 256 threads) so
 // that three workgroups share a CU; wide windows use tall tiles (18x28, 512 threads), where
-// the 2R-cell halo of a short tile would cost more than the lost occupancy.
+// the 2R-cell halo of a short tile would cost more than the lost occupancy. R = 2 and float
+// products at R = 4 take tall tiles too: at two waves per SIMD their registers hold the
+// inputs of the last 2R planes, which was measured faster than three waves of short tiles
+// that read the leaving plane again (FP64 products at R = 4 exceed the LDS in tall tiles).
 template <int BY_, int BT_, int WAVES_, int STRIP_>
 struct BoxCfg {
   static constexpr int BY = BY_;         // computed rows
@@ -53,15 +58,16 @@ struct BoxCfg {
 };
 using ShortTile = BoxCfg<14, 256, 3, 0>;
 using TallTile = BoxCfg<28, 512, 2, 8>;
-template <int R>
-using TileFor = typename std::conditional<(R <= 4), ShortTile, TallTile>::type;
+template <int R, typename T>
+using TileFor = typename std::conditional<(R == 1 || R == 3 || (R == 4 && sizeof(T) == 8)),
+                                          ShortTile, TallTile>::type;
 
 // Waves per SIMD of a (radius, precision) pair: the tile's, except double products with
 // R >= 3, whose LDS buffer leaves room for two workgroups per CU and whose x-y windows need
 // more than the 168 registers of three waves.
 template <int R, typename T>
 constexpr int box_waves() {
-  return sizeof(T) == 8 && R >= 3 ? 2 : TileFor<R>::WAVES;
+  return sizeof(T) == 8 && R >= 3 ? 2 : TileFor<R, T>::WAVES;
 }
 
 // One buffer of 10 planes of HY rows with an odd row stride (conflict-free row-per-lane
@@ -70,7 +76,7 @@ constexpr int box_waves() {
 // two of the five barriers of a step: the y pass no longer works in place, and the gradient
 // epilogue runs two planes behind the window instead of one, on planes written in earlier
 // steps.
-template <int R, typename T, class C = TileFor<R>>
+template <int R, typename T, class C = TileFor<R, T>>
 struct BoxLds {
   static constexpr int HX = kBX + 2 * R;
   static constexpr int HY = C::BY + 2 * R;
@@ -133,7 +139,7 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
                                          unsigned char* smem) {
   static_assert(!kX || sizeof(T) == 8, "exact statistics need FP64 filter sums");
   using L = BoxLds<R, T>;
-  using C = TileFor<R>;
+  using C = TileFor<R, T>;
   constexpr int kBT = C::BT, kBN = C::BN, kBOY = C::BOY, kYP = C::YP, kBYP = C::BYP;
   constexpr int HX = L::HX;
   constexpr int HY = L::HY;
@@ -187,10 +193,11 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
   // groups i0 .. i1 - 1; the plane's base addresses are uniform, so each load is a scalar
   // base plus this thread's offset
   float pn[NPF][4], po[NPF][4];
-  // R = 1: the inputs of the last 2R = 2 arriving planes stay in registers (rg[0] the older),
-  // so the plane leaving the window is not read again (wider windows have no registers left
-  // for their 2R planes)
-  constexpr int kRing = R == 1 && kRingOK ? 2 * R : 0;
+  // the inputs of the last 2R arriving planes stay in registers (rg[0] the oldest) where the
+  // registers allow, so that the plane leaving the window is not read again: R = 1, and tall
+  // tiles (two waves per SIMD) up to R = 4 (wider windows have no registers left for their
+  // 2R planes)
+  constexpr int kRing = (R == 1 || (R <= 4 && L::split)) && kRingOK ? 2 * R : 0;
   float rg[kRing > 0 ? kRing : 1][NPF][4];
   auto load = [&](float (&pf)[NPF][4], int za, int i0, int i1) {
     // za lies in [z0 - 1 - R, z1 + R] and the grid holds the support (nz >= 2R + 1), so one
@@ -481,16 +488,9 @@ __device__ __forceinline__ void box_body(const FilterArgs& A, const WidthArgs& W
 // kOut: which optional gradient-epilogue outputs the call can store (0: none, 1: the gradient
 // and Q only, 2: any); the others, their stores and (below 2) the KC scalars compile away,
 // which also keeps the kernel's scalar registers from spilling
-// The all-outputs level of the float32 8h kernel needs more than the 168 registers of three
-// waves per SIMD (its float32 statistics sums beside every closure output); it runs at two.
 template <int R, typename T, int kOut>
-constexpr int box_waves_out() {
-  return kOut == 2 && R == 4 && sizeof(T) == 4 ? 2 : box_waves<R, T>();
-}
-
-template <int R, typename T, int kOut>
-__global__ void __launch_bounds__(TileFor<R>::BT)
-    __attribute__((amdgpu_waves_per_eu(box_waves_out<R, T, kOut>(), box_waves_out<R, T, kOut>())))
+__global__ void __launch_bounds__((TileFor<R, T>::BT))
+    __attribute__((amdgpu_waves_per_eu(box_waves<R, T>(), box_waves<R, T>())))
     k_box1(FilterArgs A) {
   __shared__ double smem[BoxLds<R, T>::doubles];
   int item;
@@ -504,7 +504,7 @@ __global__ void __launch_bounds__(TileFor<R>::BT)
 // Exact statistics (FP64 filter sums): one instance per radius, with every output the call
 // may store.
 template <int R>
-__global__ void __launch_bounds__(TileFor<R>::BT)
+__global__ void __launch_bounds__((TileFor<R, double>::BT))
     __attribute__((amdgpu_waves_per_eu(box_waves<R, double>(), box_waves<R, double>())))
     k_box1_exact(FilterArgs A) {
   __shared__ double smem[BoxLds<R, double>::doubles];
@@ -515,7 +515,7 @@ __global__ void __launch_bounds__(TileFor<R>::BT)
 
 template <int R, typename T>
 BoxGeom geom_of() {
-  using C = TileFor<R>;
+  using C = TileFor<R, T>;
   return BoxGeom{kBOX, C::BOY, C::BT, C::BT / 64, BoxLds<R, T>::blocks_per_cu, C::STRIP};
 }
 
@@ -524,16 +524,16 @@ hipError_t launch_of(const FilterArgs& a, int nblocks, hipStream_t s) {
   const WidthArgs& w = a.wa;
   if constexpr (sizeof(T) == 8) {
     if (w.partials && w.exact_stats) {
-      hipLaunchKernelGGL((k_box1_exact<R>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
+      hipLaunchKernelGGL((k_box1_exact<R>), dim3(nblocks), dim3(TileFor<R, double>::BT), 0, s, a);
       return hipGetLastError();
     }
   }
   if (w.tau_gm || w.tau_smag || w.k_sgs || w.nu_t || w.omega_t)
-    hipLaunchKernelGGL((k_box1<R, T, 2>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
+    hipLaunchKernelGGL((k_box1<R, T, 2>), dim3(nblocks), dim3(TileFor<R, T>::BT), 0, s, a);
   else if (w.grad || w.q_crit)
-    hipLaunchKernelGGL((k_box1<R, T, 1>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
+    hipLaunchKernelGGL((k_box1<R, T, 1>), dim3(nblocks), dim3(TileFor<R, T>::BT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_box1<R, T, 0>), dim3(nblocks), dim3(TileFor<R>::BT), 0, s, a);
+    hipLaunchKernelGGL((k_box1<R, T, 0>), dim3(nblocks), dim3(TileFor<R, T>::BT), 0, s, a);
   return hipGetLastError();
 }
 
