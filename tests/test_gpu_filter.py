@@ -112,6 +112,9 @@ CASES = [
     ("ragged_box16_tall", (41, 57, 34), F.BOX, 16),
     ("support_box16_tall", (17, 17, 17), F.BOX, 16),  # window as wide as the grid
     ("support_box10_tall", (11, 30, 11), F.BOX, 10),
+    # 4h and 8h (float) run tall tiles holding the inputs of their last 2R planes in registers
+    ("ragged_box4_tall", (45, 59, 38), F.BOX, 4),
+    ("support_box8_tall", (9, 9, 9), F.BOX, 8),
     ("gauss4_40", (40, 36, 33), F.GAUSS, 4),
     # FP32 general taps with ragged x (no 16-byte rows), y and z (the last x-y workgroup
     # marches fewer than 8 planes)
